@@ -1,0 +1,288 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the D3Q19 step on one MI355X.
+
+Workload (default): D3Q19 BGK lid-driven cavity 256^3, FP32 populations in two
+arrays, tau 0.6, lid velocity 0.1 in x, from rest. A step is one fused pull
+stream-collide pass over all 256^3 points (Mawson & Revell, Algorithm 3).
+MLUPS counts every lattice point, solid or fluid (the paper's convention).
+
+Printed JSON line (rank 0, stdout): the contract fields, plus
+  roofline      achieved HBM GB/s of the step kernel from the algorithmic
+                152 B per point (19 loads + 19 stores of 4 B, Section 4.1)
+                over its average duration, vs the 8 TB/s MI355X peak;
+  cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample;
+  extra         16-bit offset storage (two-array and in-place AA) rates, the
+                adjoint reverse sweep rate, the measured copy ceiling, and the
+                per-step time distribution with its periodogram peak.
+Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, decimal GB/s
+BYTES_PER_POINT = {"f32": 152, "f16": 76, "bf16": 76}   # 19 loads + 19 stores
+ADJOINT_BYTES_PER_POINT = 152 + 264  # recompute step + reverse step (see DESIGN)
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for name in ("d3q19.hpp", "kernels_step.hip", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_1309_1983_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def time_steps(lat, steps, torch):
+    """Average ms per step over `steps` back-to-back launches, with HIP events
+    recorded on the lattice's stream."""
+    s = lat.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(s)
+    lat.step(steps)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cavity_lattice(n, storage, pattern, tau, lid, block=None):
+    import workloads as W
+    from paper_1309_1983_amd import Lattice
+    flags = W.cavity_flags(n, n, n)
+    lat = Lattice(n, n, n, tau, flags=flags, storage=storage, pattern=pattern, block=block)
+    lat.set_wall_velocity(lid)
+    return lat
+
+
+def copy_ceiling(torch, gib=2.0, reps=20):
+    from paper_1309_1983_amd import copy_f32
+    n = int(gib * (1 << 30) / 4)
+    a = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        copy_f32(a, b)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        copy_f32(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    assert torch.equal(a[:1000], b[:1000])
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def step_time_distribution(torch, n, steps, tau, lid):
+    """Per-step durations from the library's event log; periodogram peak of
+    the series sampled at the mean step time (the paper's Fourier analysis of
+    iteration times, Section 6)."""
+    import workloads as W
+    from paper_1309_1983_amd import Lattice
+    flags = W.cavity_flags(n, n, n)
+    lat = Lattice(n, n, n, tau, flags=flags, timing=steps)
+    lat.set_wall_velocity(lid)
+    lat.step(50)
+    lat.step_times()
+    lat.step(steps)
+    t = lat.step_times(cap=steps).astype(np.float64)
+    lat.close()
+    mean, sd = float(t.mean()), float(t.std())
+    x = t - t.mean()
+    spec = np.abs(np.fft.rfft(x)) ** 2
+    freqs = np.fft.rfftfreq(len(x), d=mean * 1e-3)
+    k = int(np.argmax(spec[1:]) + 1) if len(spec) > 1 else 0
+    amp = float(np.sqrt(spec[k] * 2) / len(x)) if k else 0.0
+    return {
+        "steps": int(len(t)), "mean_ms": mean, "std_ms": sd,
+        "p50_ms": float(np.percentile(t, 50)), "p99_ms": float(np.percentile(t, 99)),
+        "max_ms": float(t.max()), "spikes_gt_mean_5sd": int(np.sum(t > mean + 5 * sd)),
+        "fft_peak_hz": float(freqs[k]) if k else None,
+        "fft_peak_amp_ms": amp, "fft_peak_amp_over_std": amp / sd if sd > 0 else None,
+    }
+
+
+def adjoint_rate(torch, n, T, K, tau):
+    """Reverse sweep (segment recompute + reverse steps) of a T-step rollout
+    of the per-point-force duct, in MLUPS = points * T / time."""
+    import workloads as W
+    from paper_1309_1983_amd import Lattice
+    flags = W.duct_flags(n, n, n)
+    N = flags.size
+    lat = Lattice(n, n, n, tau, flags=flags)
+    F = torch.from_numpy(W.random_force_field(N, 1, 1e-5).astype(np.float32)).cuda()
+    lat.set_force(F)
+    lat.forward_checkpointed(T, K)
+    g = torch.full((3, N), 1e-3, device="cuda")
+    lat.adjoint(g)  # warm (allocates the adjoint buffers)
+    lat.forward_checkpointed(T, K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.adjoint(g)   # synchronises before returning
+    dt = time.perf_counter() - t0
+    gb = lat.device_bytes() / 1e9
+    lat.close()
+    return N * T / dt / 1e6, gb
+
+
+def cpu_baseline(n, tau, lid, budget_s=12.0):
+    """The FP64 oracle on the host: whole 256^3 cavity steps, as many as fit
+    the time budget (at least one)."""
+    import oracle
+    import workloads as W
+    flags = W.cavity_flags(n, n, n)
+    N = flags.size
+    lat = oracle.Lattice(n, n, n, float(np.float32(tau)), flags=flags, uw=(float(np.float32(lid)), 0, 0))
+    s = oracle.init_equilibrium(N)
+    out = np.empty_like(s)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        out = lat.step(s)
+        s, out = out, s
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= 50:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": N * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the full {n}^3 cavity ({dt:.1f} s, "
+                      f"{platform.processor() or platform.machine()}, nproc={os.cpu_count()})"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--block", type=int, nargs=2, default=None)
+    ap.add_argument("--sweep", action="store_true", help="work-group shape sweep (stderr)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--timing-steps", type=int, default=10000)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path is "
+              "single-GPU; multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1309_1983_amd
+    paper_1309_1983_amd.lib()
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+
+    n, tau, lid = args.n, 0.6, 0.1
+    N = n ** 3
+    workload = f"cavity{n}"
+    log(f"device {torch.cuda.get_device_name(0)}; workload {workload}")
+
+    if args.sweep:
+        for bx, by in [(64, 1), (128, 1), (256, 1), (64, 4), (128, 2), (256, 2), (256, 4), (32, 8)]:
+            lat = cavity_lattice(n, "f32", "ab", tau, lid, block=(bx, by))
+            lat.step(args.warmup)
+            ms = time_steps(lat, max(200, args.steps // 2), torch)
+            lat.close()
+            log(f"sweep block {bx}x{by}: {ms:.4f} ms/step, {N / ms / 1e3:.0f} MLUPS, "
+                f"{BYTES_PER_POINT['f32'] * N / ms / 1e6:.0f} GB/s")
+
+    # ---- headline: FP32 two-array step ----
+    lat = cavity_lattice(n, "f32", "ab", tau, lid, block=args.block)
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} FP32 AB steps")
+    ms = time_steps(lat, args.steps, torch)
+    lat.check_finite()
+    lat.close()
+    mlups = N / ms / 1e3
+    achieved = BYTES_PER_POINT["f32"] * N / (ms * 1e-3) / 1e9
+    traffic = load_traffic(workload)
+    line = {
+        "metric": "MLUPS and % HBM roofline, D3Q19 FP32 256^3; FP16-storage and adjoint MLUPS",
+        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"D3Q19 BGK lid-driven cavity {n}^3, FP32 two-array pull step, "
+                               f"halfway bounce-back walls, lid 0.1 in x, tau 0.6, from rest",
+                   "nx": n, "ny": n, "nz": n, "storage": "f32", "pattern": "ab",
+                   "block": list(args.block) if args.block else "default"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "bytes_per_point": BYTES_PER_POINT["f32"],
+                     "kernel": "k_step_ab<StF32, FORCE_NONE, collide>"},
+    }
+    log(f"FP32 AB: {ms:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s "
+        f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+
+    if not args.no_extra:
+        extra = {}
+        cc = copy_ceiling(torch)
+        extra["copy_ceiling_gbs"] = round(cc, 1)
+        line["roofline"]["frac_of_copy_ceiling"] = round(achieved / cc, 4)
+        log(f"copy ceiling {cc:.0f} GB/s")
+        for storage, pattern in (("f16", "ab"), ("bf16", "ab"), ("f16", "aa"), ("f32", "aa")):
+            lat = cavity_lattice(n, storage, pattern, tau, lid)
+            lat.step(args.warmup)
+            m = time_steps(lat, args.steps, torch)
+            lat.close()
+            bpp = BYTES_PER_POINT[storage]
+            gbs = bpp * N / (m * 1e-3) / 1e9
+            extra[f"{storage}_{pattern}"] = {"mlups": round(N / m / 1e3, 1), "ms_per_step": round(m, 5),
+                                             "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                             "bytes_per_point": bpp}
+            log(f"{storage} {pattern}: {m:.4f} ms/step, {N / m / 1e3:.0f} MLUPS, {gbs:.0f} GB/s")
+        try:
+            ar, gb = adjoint_rate(torch, n, T=200, K=50, tau=0.7)
+            extra["adjoint"] = {"mlups": round(ar, 1), "T": 200, "K": 50, "device_gb": round(gb, 1),
+                                "workload": f"duct {n}^3, per-point force, tau 0.7",
+                                "gbs_alg": round(ar * 1e6 * ADJOINT_BYTES_PER_POINT / 1e9, 1)}
+            log(f"adjoint: {ar:.0f} MLUPS (reverse sweep incl. recompute), {gb:.0f} GB on device")
+        except Exception as e:  # noqa: BLE001
+            extra["adjoint"] = {"error": str(e)}
+        if args.timing_steps > 0:
+            log(f"per-step timing log over {args.timing_steps} steps")
+            extra["step_time"] = step_time_distribution(torch, n, args.timing_steps, tau, lid)
+        line["extra"] = extra
+
+    if not args.no_cpu:
+        log("CPU baseline (FP64 oracle)")
+        line["cpu_baseline"] = cpu_baseline(n, tau, lid)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D3Q19 lattice Boltzmann library.
+ *
+ * The library implements the fused pull iteration of Mawson & Revell,
+ * "Memory transfer optimization for a lattice Boltzmann solver on Kepler
+ * architecture nVidia GPUs" (Section 4.2, Algorithm 3): every fluid lattice
+ * point gathers its 19 populations from x - e_i, applies the boundary rule,
+ * forms rho and u (Eqs. (6)-(7)), the equilibrium (Eq. (5)) and the BGK
+ * collision (Eqs. (2)-(3)), and stores the result in a second copy of the
+ * population array (Section 4.1, footnote on the redundant copy).
+ *
+ * Conventions shared by every call:
+ *   - Lattice point index: c = (z*ny + y)*nx + x, x fastest (Section 4.1).
+ *     N = nx*ny*nz. Population i of point c is element i*N + c of a
+ *     [19][N] array (structure of arrays, Section 4.1).
+ *   - Velocity set: the 19 vectors of Eq. (4), in that order.
+ *   - Flags (one byte per point): 0 = fluid, 1 = resting wall, 2 = moving
+ *     wall. Walls are halfway bounce-back: a fluid point whose neighbour
+ *     x - e_i is solid takes the population it sent towards that wall,
+ *     s_opp(i)(x), plus 6 w_i (e_i . u_wall) for a moving wall (wall density
+ *     1). The box is periodic in x, y and z; walls come only from flags.
+ *   - Body force (optional): Guo forcing, u = (m + F/2)/rho and source
+ *     (1 - 1/(2 tau)) w_i [3(e_i - u) + 9 (e_i . u) e_i] . F.
+ *   - The state is the array of post-collision populations. Values stored
+ *     at solid points are unspecified (no fluid point reads them; the
+ *     macroscopic output reports rho = 0, u = 0 there).
+ *   - Pointers named *_dev are device pointers (HIP global memory on the
+ *     lattice's device); pointers named *_host are host memory. Vector
+ *     fields are [3][N] float, component slowest.
+ *   - Every call that takes device pointers enqueues its work on the
+ *     lattice's HIP stream and returns before the GPU finishes, unless
+ *     stated otherwise. The caller keeps device buffers alive until the
+ *     stream has passed the work.
+ *   - Errors are status codes; no call throws. A failed HIP call makes the
+ *     lattice's error sticky: every later call on it returns
+ *     LBM_ERR_DEVICE (LBM_ERR_STATE for lbm_step). lbm_last_error() gives
+ *     a message for the calling thread's last failure.
+ *   - One lattice must not be used from two host threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lbm_status {
+    LBM_OK = 0,
+    LBM_ERR_INVALID = 1,   /* bad argument; nothing was changed */
+    LBM_ERR_OOM = 2,       /* device or host allocation failed */
+    LBM_ERR_DEVICE = 3,    /* a HIP call failed; the lattice is now unusable */
+    LBM_ERR_STATE = 4,     /* call not valid in the lattice's current state */
+    LBM_ERR_NONFINITE = 5  /* a finite-value check found NaN or Inf */
+} lbm_status;
+
+/* Population storage in HBM. Arithmetic is always FP32. The 16-bit forms
+ * store the offset f_i - w_i rounded to nearest even. */
+typedef enum lbm_storage {
+    LBM_STORAGE_F32 = 0,
+    LBM_STORAGE_F16 = 1,   /* IEEE binary16 offsets */
+    LBM_STORAGE_BF16 = 2   /* bfloat16 offsets */
+} lbm_storage;
+
+/* AB: two population arrays, swapped after every step (Section 4.1).
+ * AA: one array updated in place by alternating a gather/scatter step and a
+ *     local step (each work-item reads and writes the same 19 slots). */
+typedef enum lbm_pattern {
+    LBM_PATTERN_AB = 0,
+    LBM_PATTERN_AA = 1
+} lbm_pattern;
+
+typedef struct lbm_options {
+    int storage;          /* lbm_storage */
+    int pattern;          /* lbm_pattern */
+    void* hip_stream;     /* hipStream_t to launch on; NULL = the null stream */
+    int block_x;          /* work-group shape for the step kernels; 0 = default */
+    int block_y;          /*   (block_x * block_y <= 1024, block_x >= 1) */
+    int timing_capacity;  /* > 0: record a HIP event after every step (ring of
+                             this many) for lbm_step_times */
+    int check_interval;   /* > 0: lbm_step checks for non-finite values every
+                             this many steps (synchronises the stream) */
+    int device;           /* HIP device ordinal; -1 = the current device */
+    int cells_per_lane;   /* AB step: 0 = automatic (4 when nx % 4 == 0),
+                             1 = one point per work-item, 4 = four
+                             consecutive x-points per work-item (needs
+                             nx % 4 == 0 and block_x * block_y <= 256;
+                             block_x then counts work-items) */
+} lbm_options;
+
+typedef struct lbm_lattice lbm_lattice;
+
+/* Fills *opt with the defaults: F32, AB, null stream, default block shape,
+ * no timing, no checks, current device. */
+void lbm_options_default(lbm_options* opt);
+
+/*
+ * Creates a lattice of nx*ny*nz points with relaxation time tau (Eq. (2)),
+ * at rest (rho = 1, u = 0: f_i = w_i). flags_host: N bytes in index order,
+ * or NULL for all fluid; copied, so the caller may free it on return.
+ * Errors: LBM_ERR_INVALID if any n <= 0, N >= 2^30, tau <= 0.5 or not
+ * finite, a flag value > 2, or out == NULL; LBM_ERR_OOM; LBM_ERR_DEVICE.
+ * All argument checks happen before any HIP call.
+ */
+lbm_status lbm_create(int nx, int ny, int nz, float tau, const uint8_t* flags_host,
+                      lbm_lattice** out);
+
+/* As lbm_create with explicit options (opt == NULL: defaults). Errors as
+ * lbm_create, plus LBM_ERR_INVALID for an unknown storage/pattern or a bad
+ * block shape. */
+lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags_host,
+                         const lbm_options* opt, lbm_lattice** out);
+
+/* Releases everything the library allocated for the lattice (after waiting
+ * for its stream). NULL is a no-op. */
+void lbm_destroy(lbm_lattice* lat);
+
+/* Lattice sizes and storage, for the caller's bookkeeping. */
+lbm_status lbm_get_info(const lbm_lattice* lat, int* nx, int* ny, int* nz, int* storage,
+                        int* pattern);
+
+/* Changes the stream later work is launched on (NULL = null stream). */
+lbm_status lbm_set_stream(lbm_lattice* lat, void* hip_stream);
+
+/* Relaxation time (Eq. (2)); tau > 0.5. Invalidates a recorded trajectory. */
+lbm_status lbm_set_tau(lbm_lattice* lat, float tau);
+
+/* Velocity of all flag-2 points (Section 5 uses a moving lid). Each
+ * component must be finite and |u| < 0.3 (low-Mach guard). */
+lbm_status lbm_set_wall_velocity(lbm_lattice* lat, float ux, float uy, float uz);
+
+/* Uniform body force (Guo forcing); clears a force field. Invalidates a
+ * recorded trajectory. */
+lbm_status lbm_set_force_uniform(lbm_lattice* lat, float fx, float fy, float fz);
+
+/* Per-point body force F_dev: [3][N] float on the device, copied into the
+ * lattice (the caller's buffer may be freed once the stream has passed the
+ * copy). NULL removes the field (force becomes zero). Invalidates a
+ * recorded trajectory. */
+lbm_status lbm_set_force_field(lbm_lattice* lat, const float* F_dev);
+
+/* f = f^eq(rho, u) at every point (Eq. (5)); rho_dev [N] or NULL (rho = 1),
+ * u_dev [3][N] or NULL (u = 0). */
+lbm_status lbm_init_equilibrium(lbm_lattice* lat, const float* rho_dev, const float* u_dev);
+
+/* Enqueues n fused pull steps (Algorithm 3). n = 0 is a no-op.
+ * Errors: LBM_ERR_INVALID for n < 0; LBM_ERR_STATE after a device error;
+ * LBM_ERR_NONFINITE when a due check (check_interval) finds NaN/Inf. */
+lbm_status lbm_step(lbm_lattice* lat, int n);
+
+/* Writes rho = sum_i s_i and u = (sum_i e_i s_i - F/2)/rho (Eqs. (6)-(7) on
+ * the post-collision state) into rho_dev [N] and u_dev [3][N]; solid points
+ * get rho = 0, u = 0. Either pointer may be NULL to skip it, not both. */
+lbm_status lbm_macros(lbm_lattice* lat, float* rho_dev, float* u_dev);
+
+/* Copies the state out as plain populations f[19][N] float (offsets added
+ * back, the AA layout resolved). */
+lbm_status lbm_get_populations(lbm_lattice* lat, float* f_dev);
+
+/* Replaces the state with f_dev [19][N] float (plain populations; 16-bit
+ * storage rounds the offsets). Invalidates a recorded trajectory. */
+lbm_status lbm_set_populations(lbm_lattice* lat, const float* f_dev);
+
+/* Test hook: n steps of pull streaming with bounce-back and no collision
+ * and no moving-wall term (an exact permutation of the stored values). */
+lbm_status lbm_debug_stream_only(lbm_lattice* lat, int n);
+
+/*
+ * Runs T steps from the current state and keeps the states at steps 0, K,
+ * 2K, ... in device memory for lbm_adjoint (checkpoint-every-K). A last
+ * segment shorter than K is allowed. F32 storage and the AB pattern only.
+ * Errors: LBM_ERR_INVALID (T < 0, K <= 0); LBM_ERR_STATE (other storage or
+ * pattern); LBM_ERR_OOM.
+ */
+lbm_status lbm_forward_checkpointed(lbm_lattice* lat, int T, int K);
+
+/*
+ * Discrete adjoint of the rollout recorded by lbm_forward_checkpointed.
+ * dL_du_dev: [3][N] gradient of a scalar loss with respect to u(T) as
+ * returned by lbm_macros (values at solid points are ignored). Writes
+ * grad_F_dev [3][N] = dL/dF (overwritten; zero at solid points) and
+ * *grad_tau_host = dL/dtau. Recomputes each segment from its checkpoint,
+ * then runs the reverse step for every time step of the segment.
+ * Synchronises the stream before returning (grad_tau is a host value).
+ * Errors: LBM_ERR_STATE without a valid trajectory (parameters, state or
+ * force changed since it was recorded); LBM_ERR_INVALID; LBM_ERR_OOM.
+ */
+lbm_status lbm_adjoint(lbm_lattice* lat, const float* dL_du_dev, float* grad_F_dev,
+                       double* grad_tau_host);
+
+/* Checks every stored population of the fluid points for NaN/Inf.
+ * Synchronises. Returns LBM_OK or LBM_ERR_NONFINITE. */
+lbm_status lbm_check_finite(lbm_lattice* lat);
+
+/* Per-step durations (ms) of the most recent steps recorded with
+ * timing_capacity > 0, oldest first: at most cap values into ms_host,
+ * *count = number written. Synchronises. Clears the log. */
+lbm_status lbm_step_times(lbm_lattice* lat, float* ms_host, int cap, int* count);
+
+/* Waits for all work enqueued on the lattice's stream. */
+lbm_status lbm_sync(lbm_lattice* lat);
+
+/* Device bytes the library holds for this lattice. */
+size_t lbm_device_bytes(const lbm_lattice* lat);
+
+/* Static name of a status value. */
+const char* lbm_status_string(lbm_status st);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char* lbm_last_error(void);
+
+/*
+ * Bandwidth probe used to state the measured copy ceiling of the device
+ * (the paper quotes measured rather than nominal bandwidth, Section 2.2):
+ * dst[k] = src[k] for k < n floats, on the given stream, with the same
+ * one-element-per-work-item shape as the step kernels.
+ */
+lbm_status lbm_copy_f32(const float* src_dev, float* dst_dev, size_t n, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

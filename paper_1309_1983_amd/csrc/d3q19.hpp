@@ -1,0 +1,235 @@
+// Device-side building blocks of the D3Q19 step for gfx950.
+//
+// Velocity set of Eq. (4) and weights stated after Eq. (5) (Mawson & Revell,
+// Section 3.1), population storage codecs, periodic neighbour indexing for
+// the pull gather of Algorithm 3, and the BGK collision (Eqs. (2)-(3), (5)-(7))
+// with Guo forcing, evaluated in FP32 on offsets h_i = f_i - w_i.
+//
+// Compiled with -ffp-contract=off: every fused multiply-add is an explicit
+// fmaf, so each kernel that inlines these functions performs bit-identical
+// arithmetic (the AB and AA patterns must agree bit for bit).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace d3q19 {
+
+constexpr int Q = 19;
+
+// Eq. (4), i = 0..18.
+constexpr int EX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1};
+constexpr int EY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int EZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, 1, -1};
+// e_OPP[i] = -e_i: the pairs (1,2), (3,4), ..., (17,18).
+constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+
+__host__ __device__ constexpr float weight(int i)
+{
+    return i == 0 ? 1.0f / 3.0f : (i <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
+}
+
+// Flag byte: bits 0-1 cell type (0 fluid, 1 wall, 2 moving wall); bit 2 set on
+// fluid cells with at least one solid neighbour (computed at creation).
+constexpr uint8_t TYPE_MASK = 3;
+constexpr uint8_t MOVING = 2;
+constexpr uint8_t NEAR_WALL = 4;
+// bit 3 set on fluid cells with at least one moving-wall neighbour.
+constexpr uint8_t NEAR_MOVING = 8;
+
+// ---------------------------------------------------------------------------
+// Storage codecs. raw_t is what lives in HBM; off() decodes the offset
+// f_i - w_i in FP32, enc() encodes an offset (round to nearest even), plain()
+// decodes the plain population.
+// ---------------------------------------------------------------------------
+struct StF32 {
+    using raw_t = float;
+    using bits_t = float;   // element type of vector memory accesses
+    static __device__ __forceinline__ float off_b(bits_t b, int i) { return b - weight(i); }
+    static __device__ __forceinline__ bits_t enc_b(float h, int i) { return weight(i) + h; }
+    static __device__ __forceinline__ float off(raw_t r, int i) { return r - weight(i); }
+    static __device__ __forceinline__ raw_t enc(float h, int i) { return weight(i) + h; }
+    static __device__ __forceinline__ float plain(raw_t r, int) { return r; }
+    static __device__ __forceinline__ raw_t from_plain(float f, int) { return f; }
+};
+
+struct StF16 {
+    using raw_t = _Float16;
+    using bits_t = uint16_t;
+    static __device__ __forceinline__ float off_b(bits_t b, int) { return (float)__builtin_bit_cast(_Float16, b); }
+    static __device__ __forceinline__ bits_t enc_b(float h, int) { return __builtin_bit_cast(uint16_t, (_Float16)h); }
+    static __device__ __forceinline__ float off(raw_t r, int) { return (float)r; }
+    static __device__ __forceinline__ raw_t enc(float h, int) { return (_Float16)h; }
+    static __device__ __forceinline__ float plain(raw_t r, int i) { return weight(i) + (float)r; }
+    static __device__ __forceinline__ raw_t from_plain(float f, int i) { return (_Float16)(f - weight(i)); }
+};
+
+struct StBF16 {
+    using raw_t = __bf16;
+    using bits_t = uint16_t;
+    static __device__ __forceinline__ float off_b(bits_t b, int) { return __uint_as_float((uint32_t)b << 16); }
+    static __device__ __forceinline__ bits_t enc_b(float h, int) { return __builtin_bit_cast(uint16_t, (__bf16)h); }
+    static __device__ __forceinline__ float off(raw_t r, int) { return (float)r; }
+    static __device__ __forceinline__ raw_t enc(float h, int) { return (__bf16)h; }
+    static __device__ __forceinline__ float plain(raw_t r, int i) { return weight(i) + (float)r; }
+    static __device__ __forceinline__ raw_t from_plain(float f, int i) { return (__bf16)(f - weight(i)); }
+};
+
+// Four consecutive elements as one memory access (4-byte or 2-byte aligned:
+// gfx950 global memory accepts element-aligned vector accesses).
+template <class B>
+struct V4 {
+    typedef B t __attribute__((ext_vector_type(4), aligned(sizeof(B))));
+};
+
+template <class B>
+__device__ __forceinline__ typename V4<B>::t ld4(const B* base, uint32_t idx)
+{
+    return *reinterpret_cast<const typename V4<B>::t*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(B));
+}
+template <class B>
+__device__ __forceinline__ void st4(B* base, uint32_t idx, typename V4<B>::t v)
+{
+    *reinterpret_cast<typename V4<B>::t*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(B)) = v;
+}
+
+// Element idx of one direction's plane: the byte offset is formed in 32 bits
+// (planes are < 4 GiB), so the load can take the scalar-base + 32-bit
+// vector-offset addressing form.
+template <class T>
+__device__ __forceinline__ T ld(const T* base, uint32_t idx)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void st(T* base, uint32_t idx, T v)
+{
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T)) = v;
+}
+
+struct Dims {
+    int nx, ny, nz;
+    uint32_t nxy;   // nx*ny
+    uint32_t N;     // nx*ny*nz (< 2^30)
+};
+
+// Source index of the pull gather, x - e_i with periodic wrap, for all i.
+// Offsets are added modulo 2^32 (negative offsets wrap back into range).
+__device__ __forceinline__ void pull_sources(const Dims& d, int x, int y, int z, uint32_t c,
+                                             uint32_t src[Q])
+{
+    const uint32_t oxm = (x == 0) ? (uint32_t)(d.nx - 1) : 0xffffffffu;              // to x-1
+    const uint32_t oxp = (x == d.nx - 1) ? (uint32_t)(1 - d.nx) : 1u;                // to x+1
+    const uint32_t oym = (y == 0) ? (uint32_t)(d.ny - 1) * d.nx : (uint32_t)(-d.nx); // to y-1
+    const uint32_t oyp = (y == d.ny - 1) ? (uint32_t)(1 - d.ny) * d.nx : (uint32_t)d.nx;
+    const uint32_t ozm = (z == 0) ? (uint32_t)(d.nz - 1) * d.nxy : (uint32_t)0 - d.nxy;
+    const uint32_t ozp = (z == d.nz - 1) ? (uint32_t)(1 - d.nz) * d.nxy : d.nxy;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        uint32_t s = c;
+        // pull from x - e_i: e = +1 reads the minus neighbour
+        if (EX[i] == 1) s += oxm; else if (EX[i] == -1) s += oxp;
+        if (EY[i] == 1) s += oym; else if (EY[i] == -1) s += oyp;
+        if (EZ[i] == 1) s += ozm; else if (EZ[i] == -1) s += ozp;
+        src[i] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Collision on offsets. In: h_i = p_i - w_i (pre-collision), force F (zero
+// when FORCE is false). Out: h_i <- s_i - w_i.
+//   rho = 1 + sum h_i, m = sum e_i h_i (sum e_i w_i = 0), u = (m + F/2)/rho
+//   f^eq_i - w_i = w_i [ (rho - 1) + rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u) ]
+//   s_i = p_i + omega (f^eq_i - p_i) + (1 - omega/2) G_i
+//   G_i = w_i [ 3 (e_i - u).F + 9 (e_i.u)(e_i.F) ]
+// ---------------------------------------------------------------------------
+struct Macro {
+    float drho, rho, ux, uy, uz;
+};
+
+__device__ __forceinline__ float sum_h(const float h[Q])
+{
+    return ((((h[0] + h[1]) + (h[2] + h[3])) + ((h[4] + h[5]) + (h[6] + h[7])))
+            + (((h[8] + h[9]) + (h[10] + h[11])) + ((h[12] + h[13]) + (h[14] + h[15]))))
+           + ((h[16] + h[17]) + h[18]);
+}
+__device__ __forceinline__ float mom_x(const float h[Q])
+{
+    return ((h[1] - h[2]) + (h[7] - h[8])) + ((h[9] - h[10]) + (h[15] - h[16])) + (h[18] - h[17]);
+}
+__device__ __forceinline__ float mom_y(const float h[Q])
+{
+    return ((h[3] - h[4]) + (h[7] - h[8])) + ((h[10] - h[9]) + (h[11] - h[12])) + (h[13] - h[14]);
+}
+__device__ __forceinline__ float mom_z(const float h[Q])
+{
+    return ((h[5] - h[6]) + (h[11] - h[12])) + ((h[14] - h[13]) + (h[15] - h[16])) + (h[17] - h[18]);
+}
+
+// In-step macroscopic values of pre-collision offsets (u includes +F/2).
+template <bool FORCE>
+__device__ __forceinline__ Macro macro_pre(const float h[Q], float Fx, float Fy, float Fz)
+{
+    Macro m;
+    m.drho = sum_h(h);
+    m.rho = 1.0f + m.drho;
+    const float ir = 1.0f / m.rho;
+    float mx = mom_x(h), my = mom_y(h), mz = mom_z(h);
+    if (FORCE) {
+        mx = fmaf(0.5f, Fx, mx);
+        my = fmaf(0.5f, Fy, my);
+        mz = fmaf(0.5f, Fz, mz);
+    }
+    m.ux = mx * ir;
+    m.uy = my * ir;
+    m.uz = mz * ir;
+    return m;
+}
+
+__device__ __forceinline__ float edot(int i, float ax, float ay, float az)
+{
+    float r = 0.0f;
+    if (EX[i] == 1) r = ax; else if (EX[i] == -1) r = -ax;
+    if (EY[i] == 1) r += ay; else if (EY[i] == -1) r -= ay;
+    if (EZ[i] == 1) r += az; else if (EZ[i] == -1) r -= az;
+    return r;
+}
+
+// f^eq_i - w_i given the macro state and A = drho - 1.5 rho u.u.
+__device__ __forceinline__ float heq(int i, const Macro& m, float A)
+{
+    const float eu = edot(i, m.ux, m.uy, m.uz);
+    return weight(i) * fmaf(m.rho * eu, fmaf(4.5f, eu, 3.0f), A);
+}
+
+__device__ __forceinline__ float eq_A(const Macro& m)
+{
+    const float usq = fmaf(m.ux, m.ux, fmaf(m.uy, m.uy, m.uz * m.uz));
+    return fmaf(-1.5f * m.rho, usq, m.drho);
+}
+
+// Guo source without the (1 - omega/2) factor.
+__device__ __forceinline__ float guo(int i, const Macro& m, float Fx, float Fy, float Fz, float uF)
+{
+    const float eu = edot(i, m.ux, m.uy, m.uz);
+    const float eF = edot(i, Fx, Fy, Fz);
+    return weight(i) * fmaf(9.0f * eu, eF, 3.0f * (eF - uF));
+}
+
+template <bool FORCE>
+__device__ __forceinline__ void bgk_collide(float h[Q], float omega, float cF, float Fx, float Fy,
+                                            float Fz)
+{
+    const Macro m = macro_pre<FORCE>(h, Fx, Fy, Fz);
+    const float A = eq_A(m);
+    float uF = 0.0f;
+    if (FORCE) uF = fmaf(m.ux, Fx, fmaf(m.uy, Fy, m.uz * Fz));
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        float out = fmaf(omega, heq(i, m, A) - h[i], h[i]);
+        if (FORCE) out = fmaf(cF, guo(i, m, Fx, Fy, Fz, uF), out);
+        h[i] = out;
+    }
+}
+
+}  // namespace d3q19

@@ -1,0 +1,85 @@
+// Host-side launch interface of the gfx950 kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "d3q19.hpp"
+
+namespace lbmk {
+
+enum ForceMode { FORCE_NONE = 0, FORCE_UNIFORM = 1, FORCE_FIELD = 2 };
+
+struct StepArgs {
+    d3q19::Dims d;
+    float omega;   // 1/tau
+    float cF;      // 1 - 1/(2 tau)
+    float Fx, Fy, Fz;           // uniform force (FORCE_UNIFORM)
+    float mw[d3q19::Q];         // 6 w_i (e_i . u_wall), rho_wall = 1
+};
+
+struct Launch {
+    dim3 grid, block;
+    hipStream_t stream;
+};
+
+Launch make_launch(const d3q19::Dims& d, int bx, int by, hipStream_t s);
+
+// One step. AB: reads `a`, writes `b`. AA: in place on `a`; parity 0 is the
+// gather/scatter step, parity 1 the local step.
+hipError_t launch_step(int storage, int pattern, int parity, bool collide, int force_mode,
+                       void* a, void* b, const uint8_t* flags, const float* ffield,
+                       const StepArgs& args, const Launch& L);
+
+// One AB step with four consecutive x-cells per work-item (nx % 4 == 0,
+// at most 256 work-items per work-group; the launch's grid counts quads).
+hipError_t launch_step_ab4(int storage, bool collide, int force_mode, void* a, void* b,
+                           const uint8_t* flags, const uint32_t* smask, const uint32_t* mmask,
+                           const float* ffield, const StepArgs& args, const Launch& L);
+
+// flags_out = type bits of flags_in plus NEAR_WALL / NEAR_MOVING on fluid
+// cells next to a solid / moving-wall cell; smask / mmask bit i set when
+// x - e_i is solid / a moving wall.
+hipError_t launch_mark_near_wall(const uint8_t* flags_in, uint8_t* flags_out, uint32_t* smask,
+                                 uint32_t* mmask, const d3q19::Dims& d, const Launch& L);
+
+// f = f^eq(rho, u) in the given storage (natural layout).
+hipError_t launch_init_eq(int storage, void* f, const float* rho, const float* u,
+                          const d3q19::Dims& d, const Launch& L);
+
+// Plain populations of the current state (layout = 1: AA after an odd number
+// of steps, 0 otherwise) into out [19][N] float.
+hipError_t launch_get(int storage, int layout, const void* f, const uint8_t* flags, float* out,
+                      const d3q19::Dims& d, const Launch& L);
+
+// State from plain populations, natural layout.
+hipError_t launch_set(int storage, void* f, const float* in, const d3q19::Dims& d,
+                      const Launch& L);
+
+// rho [N], u [3][N] from the current state.
+hipError_t launch_macros(int storage, int layout, int force_mode, const void* f,
+                         const uint8_t* flags, const float* ffield, float* rho, float* u,
+                         const StepArgs& args, const Launch& L);
+
+// *flag |= 1 if any stored population of a fluid cell is not finite.
+hipError_t launch_check_finite(int storage, int layout, const void* f, const uint8_t* flags,
+                               int* flag, const d3q19::Dims& d, const Launch& L);
+
+hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s);
+
+// ----------------------------- adjoint ------------------------------------
+// Seed: a = dL/ds(T) from g = dL/du(T) on the state f (F32, natural layout);
+// grad_F = -g/(2 rho) (overwritten; 0 at solid cells).
+hipError_t launch_adjoint_seed(int force_mode, const float* f, const uint8_t* flags,
+                               const float* ffield, const float* g, float* a, float* gF,
+                               const StepArgs& args, const Launch& L);
+
+// Reverse step t: a^{t+1} from bin (direct = seed layout, else gathered
+// through the transposed streaming), p from the pull gather of state s^t,
+// bout = J_C(p)^T a^{t+1}; grad_F += dC/dF^T a; taupart[block] += dC/dtau . a.
+hipError_t launch_adjoint_step(bool direct, int force_mode, const float* s, const float* bin,
+                               float* bout, float* gF, double* taupart, const uint8_t* flags,
+                               const float* ffield, const StepArgs& args, float inv_tau2,
+                               const Launch& L);
+
+}  // namespace lbmk

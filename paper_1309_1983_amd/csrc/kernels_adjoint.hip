@@ -1,0 +1,245 @@
+// Reverse-time (discrete adjoint) kernels for the FP32 two-array step.
+//
+// The forward step is s^{t+1} = C(P s^t; F, tau): P is the pull gather with
+// bounce-back of Algorithm 3 (Mawson & Revell, Section 4.2) and C the BGK
+// collision with Guo forcing (Eqs. (2)-(3), (5)-(7)). With a = dL/ds^{t+1} at
+// one cell, the transposed collision Jacobian has the structured form
+//   S     = sum_i a_i f^eq_i / rho
+//   V_al  = omega rho sum_i a_i w_i [3 e_ial + 9 (e_i.u) e_ial - 3 u_al]
+//           + (1 - omega/2) sum_i a_i w_i [-3 F_al + 9 e_ial (e_i.F)]
+//   W_be  = sum_i a_i w_i [3 (e_ibe - u_be) + 9 (e_i.u) e_ibe]
+//   (J^T a)_j = (1 - omega) a_j + omega S + sum_al V_al (e_jal - u_al) / rho
+//   dL/dF_be += V_be / (2 rho) + (1 - omega/2) W_be
+//   dL/dtau  += sum_i a_i [(p_i - f^eq_i) + G_i / 2] / tau^2
+// and the transposed gather is (P^T b)_j(x) = b_j(x + e_j) if x + e_j is
+// fluid, else b_opp(j)(x). One work-item per cell: it gathers a^{t+1}(x)
+// from the previous reverse step's b through P^T, re-gathers p = (P s^t)(x),
+// and stores b^t(x) = J_C(p)^T a^{t+1}(x); the next reverse step gathers it.
+#include "kernels.hpp"
+
+using namespace d3q19;
+
+namespace lbmk {
+
+template <int FM>
+__device__ __forceinline__ void force_at(const StepArgs& a, const float* __restrict__ ff, uint32_t c,
+                                         float& Fx, float& Fy, float& Fz)
+{
+    if (FM == FORCE_UNIFORM) {
+        Fx = a.Fx; Fy = a.Fy; Fz = a.Fz;
+    } else if (FM == FORCE_FIELD) {
+        Fx = ff[c]; Fy = ff[(size_t)a.d.N + c]; Fz = ff[2 * (size_t)a.d.N + c];
+    } else {
+        Fx = Fy = Fz = 0.0f;
+    }
+}
+
+// Seed: u = (m - F/2)/rho from the post-collision state, du_al/ds_j =
+// (e_jal - u_al)/rho, so a_j = (e_j.g - u.g)/rho; direct dL/dF = -g/(2 rho).
+template <int FM>
+__global__ __launch_bounds__(1024) void k_adj_seed(const float* __restrict__ f,
+                                                   const uint8_t* __restrict__ flags,
+                                                   const float* __restrict__ ff,
+                                                   const float* __restrict__ g,
+                                                   float* __restrict__ aout, float* __restrict__ gF,
+                                                   StepArgs a)
+{
+    const Dims& d = a.d;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= d.nx || y >= d.ny) return;
+    const uint32_t c = ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx + (uint32_t)x;
+    const size_t N = d.N;
+    if (flags[c] & TYPE_MASK) {
+#pragma unroll
+        for (int j = 0; j < Q; ++j) aout[j * N + c] = 0.0f;
+        gF[c] = 0.0f; gF[N + c] = 0.0f; gF[2 * N + c] = 0.0f;
+        return;
+    }
+    float h[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) h[j] = f[j * N + c] - weight(j);
+    float Fx, Fy, Fz;
+    force_at<FM>(a, ff, c, Fx, Fy, Fz);
+    const Macro m = macro_pre<FM != FORCE_NONE>(h, -Fx, -Fy, -Fz);
+    const float ir = 1.0f / m.rho;
+    const float gx = g[c], gy = g[N + c], gz = g[2 * N + c];
+    const float ug = fmaf(m.ux, gx, fmaf(m.uy, gy, m.uz * gz));
+#pragma unroll
+    for (int j = 0; j < Q; ++j) aout[j * N + c] = (edot(j, gx, gy, gz) - ug) * ir;
+    const float h2 = -0.5f * ir;
+    gF[c] = gx * h2;
+    gF[N + c] = gy * h2;
+    gF[2 * N + c] = gz * h2;
+}
+
+template <int FM, bool DIRECT>
+__global__ __launch_bounds__(1024) void k_adj_step(const float* __restrict__ s,
+                                                   const float* __restrict__ bin,
+                                                   float* __restrict__ bout, float* __restrict__ gF,
+                                                   double* __restrict__ taupart,
+                                                   const uint8_t* __restrict__ flags,
+                                                   const float* __restrict__ ff, StepArgs a,
+                                                   float inv_tau2)
+{
+    constexpr bool FORCE = FM != FORCE_NONE;
+    const Dims& d = a.d;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    const bool inside = x < d.nx && y < d.ny;
+    const uint32_t c = inside ? ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx + (uint32_t)x : 0u;
+    const uint8_t fl = inside ? flags[c] : (uint8_t)1;
+    float tterm = 0.0f;
+
+    if (!(fl & TYPE_MASK)) {
+        const size_t N = d.N;
+        uint32_t nb[Q];
+        pull_sources(d, x, y, z, c, nb);
+        float av[Q], h[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            av[i] = DIRECT ? bin[i * N + c] : ld(bin + i * N, nb[OPP[i]]);
+            h[i] = ld(s + i * N, nb[i]);
+        }
+        uint32_t mwmask = 0;
+        if (fl & NEAR_WALL) {
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const uint8_t nf = flags[nb[i]];
+                if (nf & TYPE_MASK) {
+                    h[i] = ld(s + OPP[i] * N, c);
+                    if (nf & MOVING) mwmask |= 1u << i;
+                }
+                // x + e_i = nb[OPP[i]] solid: the adjoint arrives by the bounced link
+                if (!DIRECT && (flags[nb[OPP[i]]] & TYPE_MASK)) av[i] = ld(bin + OPP[i] * N, c);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            h[i] = h[i] - weight(i);
+            if (i > 0 && ((mwmask >> i) & 1u)) h[i] = h[i] + a.mw[i];
+        }
+        float Fx, Fy, Fz;
+        force_at<FM>(a, ff, c, Fx, Fy, Fz);
+        const Macro m = macro_pre<FORCE>(h, Fx, Fy, Fz);
+        const float A = eq_A(m);
+        const float uF = FORCE ? fmaf(m.ux, Fx, fmaf(m.uy, Fy, m.uz * Fz)) : 0.0f;
+
+        float S = 0.0f, A0 = 0.0f;
+        float A1x = 0.0f, A1y = 0.0f, A1z = 0.0f;   // sum a w e
+        float A2x = 0.0f, A2y = 0.0f, A2z = 0.0f;   // sum a w (e.u) e
+        float A3x = 0.0f, A3y = 0.0f, A3z = 0.0f;   // sum a w (e.F) e
+        float tt = 0.0f, tg = 0.0f;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float he = heq(i, m, A);
+            S = fmaf(av[i], weight(i) + he, S);
+            const float aw = av[i] * weight(i);
+            A0 += aw;
+            const float eu = edot(i, m.ux, m.uy, m.uz);
+            const float awe = aw * eu;
+            if (EX[i]) { A1x += EX[i] * aw; A2x += EX[i] * awe; }
+            if (EY[i]) { A1y += EY[i] * aw; A2y += EY[i] * awe; }
+            if (EZ[i]) { A1z += EZ[i] * aw; A2z += EZ[i] * awe; }
+            tt = fmaf(av[i], h[i] - he, tt);
+            if (FORCE) {
+                const float eF = edot(i, Fx, Fy, Fz);
+                const float awF = aw * eF;
+                if (EX[i]) A3x += EX[i] * awF;
+                if (EY[i]) A3y += EY[i] * awF;
+                if (EZ[i]) A3z += EZ[i] * awF;
+                tg = fmaf(av[i], guo(i, m, Fx, Fy, Fz, uF), tg);
+            }
+        }
+        const float om = a.omega, cF = a.cF;
+        const float ir = 1.0f / m.rho;
+        S *= ir;
+        const float orho = om * m.rho;
+        float Vx = orho * (3.0f * A1x + 9.0f * A2x - 3.0f * m.ux * A0);
+        float Vy = orho * (3.0f * A1y + 9.0f * A2y - 3.0f * m.uy * A0);
+        float Vz = orho * (3.0f * A1z + 9.0f * A2z - 3.0f * m.uz * A0);
+        if (FORCE) {
+            Vx = fmaf(cF, 9.0f * A3x - 3.0f * Fx * A0, Vx);
+            Vy = fmaf(cF, 9.0f * A3y - 3.0f * Fy * A0, Vy);
+            Vz = fmaf(cF, 9.0f * A3z - 3.0f * Fz * A0, Vz);
+        }
+        const float Vu = fmaf(Vx, m.ux, fmaf(Vy, m.uy, Vz * m.uz));
+        const float base = om * S;
+        const float oneMinus = 1.0f - om;
+#pragma unroll
+        for (int j = 0; j < Q; ++j) {
+            const float bj = fmaf(oneMinus, av[j], base) + (edot(j, Vx, Vy, Vz) - Vu) * ir;
+            bout[j * N + c] = bj;
+        }
+        const float Wx = 3.0f * A1x - 3.0f * m.ux * A0 + 9.0f * A2x;
+        const float Wy = 3.0f * A1y - 3.0f * m.uy * A0 + 9.0f * A2y;
+        const float Wz = 3.0f * A1z - 3.0f * m.uz * A0 + 9.0f * A2z;
+        const float h2 = 0.5f * ir;
+        gF[c] += fmaf(Vx, h2, cF * Wx);
+        gF[N + c] += fmaf(Vy, h2, cF * Wy);
+        gF[2 * N + c] += fmaf(Vz, h2, cF * Wz);
+        tterm = fmaf(0.5f, tg, tt) * inv_tau2;
+    }
+
+    // Block sum of the tau terms in double with a fixed-shape LDS tree (any
+    // block size, deterministic); thread 0 adds it to this block's slot.
+    __shared__ double part[1024];
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int nthreads = blockDim.x * blockDim.y;
+    part[tid] = (double)tterm;
+    __syncthreads();
+    int span = 1;
+    while (span < nthreads) span <<= 1;
+    for (int sh = span >> 1; sh > 0; sh >>= 1) {
+        if (tid < sh && tid + sh < nthreads) part[tid] += part[tid + sh];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const size_t blk = (size_t)blockIdx.x + (size_t)gridDim.x * ((size_t)blockIdx.y + (size_t)gridDim.y * blockIdx.z);
+        taupart[blk] += part[0];
+    }
+}
+
+hipError_t launch_adjoint_seed(int fm, const float* f, const uint8_t* flags, const float* ff,
+                               const float* g, float* aout, float* gF, const StepArgs& args,
+                               const Launch& L)
+{
+    switch (fm) {
+    case FORCE_UNIFORM:
+        hipLaunchKernelGGL((k_adj_seed<FORCE_UNIFORM>), L.grid, L.block, 0, L.stream, f, flags, ff, g, aout, gF, args);
+        break;
+    case FORCE_FIELD:
+        hipLaunchKernelGGL((k_adj_seed<FORCE_FIELD>), L.grid, L.block, 0, L.stream, f, flags, ff, g, aout, gF, args);
+        break;
+    default:
+        hipLaunchKernelGGL((k_adj_seed<FORCE_NONE>), L.grid, L.block, 0, L.stream, f, flags, ff, g, aout, gF, args);
+    }
+    return hipGetLastError();
+}
+
+template <int FM>
+static hipError_t adj_fm(bool direct, const float* s, const float* bin, float* bout, float* gF,
+                         double* tp, const uint8_t* flags, const float* ff, const StepArgs& a,
+                         float it2, const Launch& L)
+{
+    if (direct)
+        hipLaunchKernelGGL((k_adj_step<FM, true>), L.grid, L.block, 0, L.stream, s, bin, bout, gF, tp, flags, ff, a, it2);
+    else
+        hipLaunchKernelGGL((k_adj_step<FM, false>), L.grid, L.block, 0, L.stream, s, bin, bout, gF, tp, flags, ff, a, it2);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(bool direct, int fm, const float* s, const float* bin, float* bout,
+                               float* gF, double* taupart, const uint8_t* flags, const float* ff,
+                               const StepArgs& args, float inv_tau2, const Launch& L)
+{
+    switch (fm) {
+    case FORCE_UNIFORM: return adj_fm<FORCE_UNIFORM>(direct, s, bin, bout, gF, taupart, flags, ff, args, inv_tau2, L);
+    case FORCE_FIELD: return adj_fm<FORCE_FIELD>(direct, s, bin, bout, gF, taupart, flags, ff, args, inv_tau2, L);
+    default: return adj_fm<FORCE_NONE>(direct, s, bin, bout, gF, taupart, flags, ff, args, inv_tau2, L);
+    }
+}
+
+}  // namespace lbmk

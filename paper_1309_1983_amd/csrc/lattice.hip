@@ -1,0 +1,719 @@
+// Host runtime of the C ABI declared in include/lbm.h.
+//
+// Owns the device buffers of a lattice (population arrays, preprocessed
+// flags, force field, checkpoints and adjoint buffers), validates every
+// argument before touching HIP, launches the kernels on the lattice's stream
+// and keeps the step bookkeeping: the AB buffer swap after each step
+// (Mawson & Revell, Section 4.1, footnote on the redundant copy), the AA
+// parity, the per-step event log, and the checkpoint-every-K rollout with
+// its reverse sweep.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "kernels.hpp"
+
+using d3q19::Q;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lbm_status fail(lbm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+size_t storage_bytes(int storage) { return storage == LBM_STORAGE_F32 ? 4 : 2; }
+
+}  // namespace
+
+struct lbm_lattice {
+    int nx = 0, ny = 0, nz = 0;
+    size_t N = 0;
+    d3q19::Dims dims{};
+    int device = 0;
+    int storage = LBM_STORAGE_F32;
+    int pattern = LBM_PATTERN_AB;
+    int bx = 256, by = 1;
+    hipStream_t stream = nullptr;
+
+    float tau = 0.6f;
+    float uw[3] = {0, 0, 0};
+    float force[3] = {0, 0, 0};
+    bool has_force_uniform = false;
+    float* d_force = nullptr;   // [3][N] when a field is set
+    bool has_force_field = false;
+
+    void* d_f[2] = {nullptr, nullptr};
+    int cur = 0;      // AB: index of the array holding the state
+    int parity = 0;   // AA: 0 natural layout, 1 shifted layout
+    uint8_t* d_flags = nullptr;
+    uint32_t* d_smask = nullptr;   // solid-neighbour bits per cell
+    uint32_t* d_mmask = nullptr;   // moving-wall-neighbour bits per cell
+    int* d_check = nullptr;
+    int cpl = 1;                   // cells per work-item of the AB step
+    int bx4 = 64, by4 = 4;         // work-group of the four-cell kernel
+
+    bool sticky = false;
+    long long steps_done = 0;
+    int check_interval = 0;
+
+    // per-step timing log
+    int timing_cap = 0;
+    std::vector<hipEvent_t> events;  // ring of timing_cap + 1
+    long long ev_recorded = 0;       // events recorded since the log was cleared
+
+    // checkpointed trajectory for the adjoint
+    std::vector<float*> ckpt;
+    int traj_T = -1, traj_K = 0;
+    long long traj_version = -1;
+    long long version = 0;           // bumped by anything that changes the dynamics/state
+    float* d_seg = nullptr;          // (K-1) states
+    int seg_cap = 0;
+    float* d_adj[2] = {nullptr, nullptr};
+    double* d_taupart = nullptr;
+    size_t taupart_n = 0;
+
+    size_t bytes = 0;
+};
+
+namespace {
+
+lbm_status hip_check(lbm_lattice* L, hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return LBM_OK;
+    if (L) L->sticky = true;
+    if (e == hipErrorOutOfMemory) return fail(LBM_ERR_OOM, "%s: %s", what, hipGetErrorString(e));
+    return fail(LBM_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(L, call)                                                 \
+    do {                                                                \
+        lbm_status _st = hip_check((L), (call), #call);                 \
+        if (_st != LBM_OK) return _st;                                  \
+    } while (0)
+
+lbm_status usable(const lbm_lattice* L)
+{
+    if (!L) return fail(LBM_ERR_INVALID, "lattice is NULL");
+    if (L->sticky) return fail(LBM_ERR_DEVICE, "lattice is in a failed state after a device error");
+    return LBM_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int now = -1;
+        if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int force_mode(const lbm_lattice* L)
+{
+    if (L->has_force_field) return lbmk::FORCE_FIELD;
+    if (L->has_force_uniform) return lbmk::FORCE_UNIFORM;
+    return lbmk::FORCE_NONE;
+}
+
+lbmk::StepArgs step_args(const lbm_lattice* L)
+{
+    lbmk::StepArgs a{};
+    a.d = L->dims;
+    const double tau = L->tau;
+    a.omega = (float)(1.0 / tau);
+    a.cF = (float)(1.0 - 0.5 / tau);
+    a.Fx = L->force[0];
+    a.Fy = L->force[1];
+    a.Fz = L->force[2];
+    for (int i = 0; i < Q; ++i) {
+        const double eu = d3q19::EX[i] * (double)L->uw[0] + d3q19::EY[i] * (double)L->uw[1]
+                          + d3q19::EZ[i] * (double)L->uw[2];
+        a.mw[i] = (float)(6.0 * (double)d3q19::weight(i) * eu);
+    }
+    return a;
+}
+
+lbmk::Launch launch_of(const lbm_lattice* L) { return lbmk::make_launch(L->dims, L->bx, L->by, L->stream); }
+
+// Only valid when the lattice uses the four-cell kernel (cpl == 4).
+lbmk::Launch launch4_of(const lbm_lattice* L)
+{
+    d3q19::Dims q = L->dims;
+    q.nx = L->nx / 4;   // the grid counts quads along x
+    return lbmk::make_launch(q, L->bx4, L->by4, L->stream);
+}
+
+void default_block(int nx, int& bx, int& by)
+{
+    if (nx >= 256) { bx = 256; by = 1; return; }
+    if ((nx & (nx - 1)) == 0) { bx = nx; by = 256 / nx; return; }
+    bx = std::min(256, (nx + 63) / 64 * 64);
+    by = std::max(1, 256 / bx);
+}
+
+template <class T>
+lbm_status dalloc(lbm_lattice* L, T** p, size_t bytes, const char* what)
+{
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? LBM_ERR_OOM : LBM_ERR_DEVICE, "hipMalloc(%zu B) for %s: %s",
+                    bytes, what, hipGetErrorString(e));
+    }
+    *p = static_cast<T*>(q);
+    L->bytes += bytes;
+    return LBM_OK;
+}
+
+void dfree(lbm_lattice* L, void* p, size_t bytes)
+{
+    if (p) {
+        (void)hipFree(p);
+        L->bytes -= std::min(L->bytes, bytes);
+    }
+}
+
+void drop_trajectory(lbm_lattice* L)
+{
+    const size_t sb = (size_t)Q * L->N * sizeof(float);
+    for (float* p : L->ckpt) dfree(L, p, sb);
+    L->ckpt.clear();
+    dfree(L, L->d_seg, sb * (size_t)L->seg_cap);
+    L->d_seg = nullptr;
+    L->seg_cap = 0;
+    L->traj_T = -1;
+    L->traj_version = -1;
+}
+
+void invalidate(lbm_lattice* L) { ++L->version; }
+
+lbm_status run_steps(lbm_lattice* L, int n, bool collide);
+
+}  // namespace
+
+extern "C" {
+
+void lbm_options_default(lbm_options* opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof *opt);
+    opt->storage = LBM_STORAGE_F32;
+    opt->pattern = LBM_PATTERN_AB;
+    opt->device = -1;
+}
+
+const char* lbm_status_string(lbm_status st)
+{
+    switch (st) {
+    case LBM_OK: return "LBM_OK";
+    case LBM_ERR_INVALID: return "LBM_ERR_INVALID";
+    case LBM_ERR_OOM: return "LBM_ERR_OOM";
+    case LBM_ERR_DEVICE: return "LBM_ERR_DEVICE";
+    case LBM_ERR_STATE: return "LBM_ERR_STATE";
+    case LBM_ERR_NONFINITE: return "LBM_ERR_NONFINITE";
+    }
+    return "LBM_ERR_UNKNOWN";
+}
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+lbm_status lbm_create(int nx, int ny, int nz, float tau, const uint8_t* flags_host, lbm_lattice** out)
+{
+    return lbm_create_ex(nx, ny, nz, tau, flags_host, nullptr, out);
+}
+
+lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags_host,
+                         const lbm_options* opt_in, lbm_lattice** out)
+{
+    g_last_error.clear();
+    if (!out) return fail(LBM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (nx <= 0 || ny <= 0 || nz <= 0) return fail(LBM_ERR_INVALID, "sizes must be positive (%d,%d,%d)", nx, ny, nz);
+    const unsigned long long N = (unsigned long long)nx * ny * nz;
+    if (N >= (1ull << 30)) return fail(LBM_ERR_INVALID, "N = %llu points exceeds 2^30", N);
+    if (nz > 65535) return fail(LBM_ERR_INVALID, "nz must be <= 65535 (got %d)", nz);
+    if (!(tau > 0.5f) || !std::isfinite(tau)) return fail(LBM_ERR_INVALID, "tau must be finite and > 0.5 (got %g)", (double)tau);
+    lbm_options opt;
+    if (opt_in) opt = *opt_in;
+    else lbm_options_default(&opt);
+    if (opt.storage < 0 || opt.storage > 2) return fail(LBM_ERR_INVALID, "unknown storage %d", opt.storage);
+    if (opt.pattern < 0 || opt.pattern > 1) return fail(LBM_ERR_INVALID, "unknown pattern %d", opt.pattern);
+    int bx = opt.block_x, by = opt.block_y;
+    if (bx == 0 && by == 0) default_block(nx, bx, by);
+    if (bx <= 0 || by <= 0 || bx * by > 1024) return fail(LBM_ERR_INVALID, "bad block shape %dx%d", bx, by);
+    if ((ny + by - 1) / by > 65535) return fail(LBM_ERR_INVALID, "ny/block_y must be <= 65535 work-groups");
+    if (opt.timing_capacity < 0 || opt.check_interval < 0) return fail(LBM_ERR_INVALID, "negative timing/check option");
+    if (opt.cells_per_lane != 0 && opt.cells_per_lane != 1 && opt.cells_per_lane != 4)
+        return fail(LBM_ERR_INVALID, "cells_per_lane must be 0, 1 or 4 (got %d)", opt.cells_per_lane);
+    int cpl = 1, bx4 = 0, by4 = 0;
+    if (opt.pattern == LBM_PATTERN_AB && nx % 4 == 0 && opt.cells_per_lane != 1) {
+        if (opt.block_x == 0 && opt.block_y == 0) {
+            bx4 = std::min(nx / 4, 64);
+            by4 = std::max(1, 256 / bx4);
+            cpl = 4;
+        } else if (bx * by <= 256) {
+            bx4 = bx; by4 = by;
+            cpl = 4;
+        }
+    }
+    if (opt.cells_per_lane == 4 && cpl != 4)
+        return fail(LBM_ERR_INVALID, "cells_per_lane = 4 needs the AB pattern, nx %% 4 == 0 and <= 256 work-items per group");
+    if (cpl == 4 && (ny + by4 - 1) / by4 > 65535) return fail(LBM_ERR_INVALID, "ny/block_y must be <= 65535 work-groups");
+    if (flags_host) {
+        for (unsigned long long c = 0; c < N; ++c)
+            if (flags_host[c] > 2) return fail(LBM_ERR_INVALID, "flag value %u at point %llu (allowed 0, 1, 2)", flags_host[c], c);
+    }
+
+    int dev = opt.device;
+    if (dev < 0) {
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return fail(LBM_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    DeviceGuard guard(dev);
+
+    lbm_lattice* L = new (std::nothrow) lbm_lattice;
+    if (!L) return fail(LBM_ERR_OOM, "host allocation failed");
+    L->nx = nx; L->ny = ny; L->nz = nz; L->N = (size_t)N;
+    L->dims.nx = nx; L->dims.ny = ny; L->dims.nz = nz;
+    L->dims.nxy = (uint32_t)nx * (uint32_t)ny;
+    L->dims.N = (uint32_t)N;
+    L->device = dev;
+    L->storage = opt.storage;
+    L->pattern = opt.pattern;
+    L->bx = bx; L->by = by;
+    L->stream = static_cast<hipStream_t>(opt.hip_stream);
+    L->tau = tau;
+    L->timing_cap = opt.timing_capacity;
+    L->check_interval = opt.check_interval;
+    L->cpl = cpl;
+    if (cpl == 4) { L->bx4 = bx4; L->by4 = by4; }
+
+    lbm_status st = LBM_OK;
+    const size_t fbytes = (size_t)Q * L->N * storage_bytes(L->storage);
+    const int nbuf = L->pattern == LBM_PATTERN_AB ? 2 : 1;
+    for (int b = 0; b < nbuf && st == LBM_OK; ++b) st = dalloc(L, &L->d_f[b], fbytes, "populations");
+    if (st == LBM_OK) st = dalloc(L, &L->d_flags, L->N, "flags");
+    if (st == LBM_OK) st = dalloc(L, &L->d_smask, L->N * sizeof(uint32_t), "neighbour masks");
+    if (st == LBM_OK) st = dalloc(L, &L->d_mmask, L->N * sizeof(uint32_t), "neighbour masks");
+    if (st == LBM_OK) st = dalloc(L, &L->d_check, sizeof(int), "check flag");
+    uint8_t* d_raw = nullptr;
+    if (st == LBM_OK) st = dalloc(L, &d_raw, L->N, "raw flags");
+    if (st == LBM_OK) {
+        hipError_t e = flags_host ? hipMemcpyAsync(d_raw, flags_host, L->N, hipMemcpyHostToDevice, L->stream)
+                                  : hipMemsetAsync(d_raw, 0, L->N, L->stream);
+        st = hip_check(L, e, "flags upload");
+    }
+    if (st == LBM_OK) st = hip_check(L, lbmk::launch_mark_near_wall(d_raw, L->d_flags, L->d_smask, L->d_mmask, L->dims, launch_of(L)), "mark_near_wall");
+    // rest state in every array (solid points keep it forever)
+    for (int b = 0; b < nbuf && st == LBM_OK; ++b)
+        st = hip_check(L, lbmk::launch_init_eq(L->storage, L->d_f[b], nullptr, nullptr, L->dims, launch_of(L)), "init");
+    if (st == LBM_OK && L->timing_cap > 0) {
+        L->events.resize((size_t)L->timing_cap + 1, nullptr);
+        for (auto& ev : L->events)
+            if (st == LBM_OK) st = hip_check(L, hipEventCreate(&ev), "hipEventCreate");
+    }
+    if (st == LBM_OK) st = hip_check(L, hipStreamSynchronize(L->stream), "create sync");
+    if (d_raw) dfree(L, d_raw, L->N);
+    if (st != LBM_OK) {
+        std::string msg = g_last_error;
+        lbm_destroy(L);
+        g_last_error = msg;
+        return st;
+    }
+    *out = L;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_lattice* L)
+{
+    if (!L) return;
+    DeviceGuard guard(L->device);
+    (void)hipStreamSynchronize(L->stream);
+    drop_trajectory(L);
+    const size_t sb = (size_t)Q * L->N * sizeof(float);
+    dfree(L, L->d_adj[0], sb);
+    dfree(L, L->d_adj[1], sb);
+    dfree(L, L->d_taupart, L->taupart_n * sizeof(double));
+    const size_t fbytes = (size_t)Q * L->N * storage_bytes(L->storage);
+    dfree(L, L->d_f[0], fbytes);
+    dfree(L, L->d_f[1], fbytes);
+    dfree(L, L->d_flags, L->N);
+    dfree(L, L->d_smask, L->N * sizeof(uint32_t));
+    dfree(L, L->d_mmask, L->N * sizeof(uint32_t));
+    dfree(L, L->d_check, sizeof(int));
+    dfree(L, L->d_force, 3 * L->N * sizeof(float));
+    for (auto ev : L->events)
+        if (ev) (void)hipEventDestroy(ev);
+    delete L;
+}
+
+lbm_status lbm_get_info(const lbm_lattice* L, int* nx, int* ny, int* nz, int* storage, int* pattern)
+{
+    if (!L) return fail(LBM_ERR_INVALID, "lattice is NULL");
+    if (nx) *nx = L->nx;
+    if (ny) *ny = L->ny;
+    if (nz) *nz = L->nz;
+    if (storage) *storage = L->storage;
+    if (pattern) *pattern = L->pattern;
+    return LBM_OK;
+}
+
+size_t lbm_device_bytes(const lbm_lattice* L) { return L ? L->bytes : 0; }
+
+lbm_status lbm_set_stream(lbm_lattice* L, void* s)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    L->stream = static_cast<hipStream_t>(s);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_tau(lbm_lattice* L, float tau)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (!(tau > 0.5f) || !std::isfinite(tau)) return fail(LBM_ERR_INVALID, "tau must be finite and > 0.5 (got %g)", (double)tau);
+    if (tau != L->tau) invalidate(L);
+    L->tau = tau;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_wall_velocity(lbm_lattice* L, float ux, float uy, float uz)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (!std::isfinite(ux) || !std::isfinite(uy) || !std::isfinite(uz))
+        return fail(LBM_ERR_INVALID, "wall velocity must be finite");
+    if (std::sqrt((double)ux * ux + (double)uy * uy + (double)uz * uz) >= 0.3)
+        return fail(LBM_ERR_INVALID, "|u_wall| must be < 0.3 (low Mach number)");
+    L->uw[0] = ux; L->uw[1] = uy; L->uw[2] = uz;
+    invalidate(L);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_force_uniform(lbm_lattice* L, float fx, float fy, float fz)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (!std::isfinite(fx) || !std::isfinite(fy) || !std::isfinite(fz))
+        return fail(LBM_ERR_INVALID, "force must be finite");
+    L->force[0] = fx; L->force[1] = fy; L->force[2] = fz;
+    L->has_force_uniform = (fx != 0.0f || fy != 0.0f || fz != 0.0f);
+    L->has_force_field = false;
+    invalidate(L);
+    return LBM_OK;
+}
+
+lbm_status lbm_set_force_field(lbm_lattice* L, const float* F_dev)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    DeviceGuard guard(L->device);
+    invalidate(L);
+    if (!F_dev) {
+        L->has_force_field = false;
+        return LBM_OK;
+    }
+    if (!L->d_force) {
+        st = dalloc(L, &L->d_force, 3 * L->N * sizeof(float), "force field");
+        if (st != LBM_OK) return st;
+    }
+    HIPCHK(L, hipMemcpyAsync(L->d_force, F_dev, 3 * L->N * sizeof(float), hipMemcpyDeviceToDevice, L->stream));
+    L->has_force_field = true;
+    L->has_force_uniform = false;
+    L->force[0] = L->force[1] = L->force[2] = 0.0f;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_equilibrium(lbm_lattice* L, const float* rho, const float* u)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    DeviceGuard guard(L->device);
+    HIPCHK(L, lbmk::launch_init_eq(L->storage, L->d_f[L->cur], rho, u, L->dims, launch_of(L)));
+    L->parity = 0;
+    invalidate(L);
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_lattice* L, int n)
+{
+    if (!L) return fail(LBM_ERR_INVALID, "lattice is NULL");
+    if (L->sticky) return fail(LBM_ERR_STATE, "lattice is in a failed state after a device error");
+    if (n < 0) return fail(LBM_ERR_INVALID, "n must be >= 0 (got %d)", n);
+    DeviceGuard guard(L->device);
+    return run_steps(L, n, true);
+}
+
+lbm_status lbm_debug_stream_only(lbm_lattice* L, int n)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (n < 0) return fail(LBM_ERR_INVALID, "n must be >= 0 (got %d)", n);
+    DeviceGuard guard(L->device);
+    return run_steps(L, n, false);
+}
+
+lbm_status lbm_macros(lbm_lattice* L, float* rho, float* u)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (!rho && !u) return fail(LBM_ERR_INVALID, "rho and u are both NULL");
+    DeviceGuard guard(L->device);
+    HIPCHK(L, lbmk::launch_macros(L->storage, L->parity, force_mode(L), L->d_f[L->cur], L->d_flags,
+                                  L->d_force, rho, u, step_args(L), launch_of(L)));
+    return LBM_OK;
+}
+
+lbm_status lbm_get_populations(lbm_lattice* L, float* f)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (!f) return fail(LBM_ERR_INVALID, "f is NULL");
+    DeviceGuard guard(L->device);
+    HIPCHK(L, lbmk::launch_get(L->storage, L->parity, L->d_f[L->cur], L->d_flags, f, L->dims, launch_of(L)));
+    return LBM_OK;
+}
+
+lbm_status lbm_set_populations(lbm_lattice* L, const float* f)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (!f) return fail(LBM_ERR_INVALID, "f is NULL");
+    DeviceGuard guard(L->device);
+    HIPCHK(L, lbmk::launch_set(L->storage, L->d_f[L->cur], f, L->dims, launch_of(L)));
+    L->parity = 0;
+    invalidate(L);
+    return LBM_OK;
+}
+
+lbm_status lbm_check_finite(lbm_lattice* L)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    DeviceGuard guard(L->device);
+    HIPCHK(L, hipMemsetAsync(L->d_check, 0, sizeof(int), L->stream));
+    HIPCHK(L, lbmk::launch_check_finite(L->storage, L->parity, L->d_f[L->cur], L->d_flags, L->d_check, L->dims,
+                                        launch_of(L)));
+    int h = 0;
+    HIPCHK(L, hipMemcpyAsync(&h, L->d_check, sizeof(int), hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(L, hipStreamSynchronize(L->stream));
+    if (h) return fail(LBM_ERR_NONFINITE, "non-finite population found after %lld steps", L->steps_done);
+    return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_lattice* L)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    DeviceGuard guard(L->device);
+    HIPCHK(L, hipStreamSynchronize(L->stream));
+    return LBM_OK;
+}
+
+lbm_status lbm_step_times(lbm_lattice* L, float* ms, int cap, int* count)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (!count || (cap > 0 && !ms) || cap < 0) return fail(LBM_ERR_INVALID, "bad output arguments");
+    *count = 0;
+    if (L->timing_cap <= 0) return fail(LBM_ERR_STATE, "timing log not enabled (timing_capacity = 0)");
+    DeviceGuard guard(L->device);
+    HIPCHK(L, hipStreamSynchronize(L->stream));
+    const long long R = (long long)L->events.size();   // ring slots
+    const long long rec = L->ev_recorded;
+    // the newest min(rec, R) events are valid; durations between consecutive ones
+    const long long valid = std::min(rec, R);
+    const long long ndur = valid > 0 ? valid - 1 : 0;
+    const long long nout = std::min<long long>(ndur, cap);
+    const long long first = rec - nout - 1;   // index of the event before the first duration
+    for (long long k = 0; k < nout; ++k) {
+        hipEvent_t a = L->events[(size_t)((first + k) % R)];
+        hipEvent_t b = L->events[(size_t)((first + k + 1) % R)];
+        float t = 0.0f;
+        HIPCHK(L, hipEventElapsedTime(&t, a, b));
+        ms[k] = t;
+    }
+    *count = (int)nout;
+    L->ev_recorded = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_copy_f32(const float* src, float* dst, size_t n, void* stream)
+{
+    if ((!src || !dst) && n) return fail(LBM_ERR_INVALID, "NULL buffer");
+    hipError_t e = lbmk::launch_copy(src, dst, n, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(LBM_ERR_DEVICE, "copy: %s", hipGetErrorString(e));
+    return LBM_OK;
+}
+
+lbm_status lbm_forward_checkpointed(lbm_lattice* L, int T, int K)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (T < 0 || K <= 0) return fail(LBM_ERR_INVALID, "need T >= 0 and K > 0 (got T=%d K=%d)", T, K);
+    if (L->storage != LBM_STORAGE_F32 || L->pattern != LBM_PATTERN_AB)
+        return fail(LBM_ERR_STATE, "the adjoint rollout needs F32 storage and the AB pattern");
+    DeviceGuard guard(L->device);
+    drop_trajectory(L);
+    const size_t sb = (size_t)Q * L->N * sizeof(float);
+    const int nck = T == 0 ? 1 : (T + K - 1) / K;
+    for (int k = 0; k < nck; ++k) {
+        float* p = nullptr;
+        st = dalloc(L, &p, sb, "checkpoint");
+        if (st != LBM_OK) { drop_trajectory(L); return st; }
+        L->ckpt.push_back(p);
+    }
+    const int segK = std::min(K, std::max(T, 1));
+    if (segK > 1) {
+        st = dalloc(L, &L->d_seg, sb * (size_t)(segK - 1), "segment store");
+        if (st != LBM_OK) { drop_trajectory(L); return st; }
+        L->seg_cap = segK - 1;
+    }
+    for (int k = 0; k < nck; ++k) {
+        HIPCHK(L, hipMemcpyAsync(L->ckpt[k], L->d_f[L->cur], sb, hipMemcpyDeviceToDevice, L->stream));
+        const int len = std::min(K, T - k * K);
+        if (len > 0) {
+            st = run_steps(L, len, true);
+            if (st != LBM_OK) { drop_trajectory(L); return st; }
+        }
+    }
+    L->traj_T = T;
+    L->traj_K = K;
+    L->traj_version = L->version;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint(lbm_lattice* L, const float* g, float* gF, double* grad_tau)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (!g || !gF || !grad_tau) return fail(LBM_ERR_INVALID, "NULL argument");
+    if (L->traj_T < 0 || L->traj_version != L->version)
+        return fail(LBM_ERR_STATE, "no valid trajectory: call lbm_forward_checkpointed after the last change");
+    DeviceGuard guard(L->device);
+    const size_t sb = (size_t)Q * L->N * sizeof(float);
+    for (int b = 0; b < 2; ++b)
+        if (!L->d_adj[b]) {
+            st = dalloc(L, &L->d_adj[b], sb, "adjoint buffer");
+            if (st != LBM_OK) return st;
+        }
+    const lbmk::Launch LA = launch_of(L);
+    const size_t nblk = (size_t)LA.grid.x * LA.grid.y * LA.grid.z;
+    if (L->taupart_n < nblk) {
+        dfree(L, L->d_taupart, L->taupart_n * sizeof(double));
+        L->d_taupart = nullptr;
+        L->taupart_n = 0;
+        st = dalloc(L, &L->d_taupart, nblk * sizeof(double), "tau partials");
+        if (st != LBM_OK) return st;
+        L->taupart_n = nblk;
+    }
+    HIPCHK(L, hipMemsetAsync(L->d_taupart, 0, nblk * sizeof(double), L->stream));
+
+    const lbmk::StepArgs args = step_args(L);
+    const int fm = force_mode(L);
+    const float inv_tau2 = (float)(1.0 / ((double)L->tau * (double)L->tau));
+    const int T = L->traj_T, K = L->traj_K;
+    const int nck = (int)L->ckpt.size();
+
+    // seed from the final state (the lattice's current array)
+    HIPCHK(L, lbmk::launch_adjoint_seed(fm, static_cast<const float*>(L->d_f[L->cur]), L->d_flags, L->d_force, g,
+                                        L->d_adj[0], gF, args, LA));
+    int ab = 0;            // d_adj[ab] holds the adjoint input of the next reverse step
+    bool direct = true;
+    for (int k = nck - 1; k >= 0 && T > 0; --k) {
+        const int t0 = k * K;
+        const int len = std::min(K, T - t0);
+        // recompute s^{t0+1} .. s^{t0+len-1} into the segment store
+        auto state = [&](int j) -> float* { return j == 0 ? L->ckpt[k] : L->d_seg + (size_t)(j - 1) * Q * L->N; };
+        for (int j = 1; j < len; ++j) {
+            if (L->cpl == 4)
+                HIPCHK(L, lbmk::launch_step_ab4(LBM_STORAGE_F32, true, fm, state(j - 1), state(j), L->d_flags,
+                                                L->d_smask, L->d_mmask, L->d_force, args, launch4_of(L)));
+            else
+                HIPCHK(L, lbmk::launch_step(LBM_STORAGE_F32, LBM_PATTERN_AB, 0, true, fm, state(j - 1), state(j),
+                                            L->d_flags, L->d_force, args, LA));
+        }
+        for (int j = len - 1; j >= 0; --j) {
+            HIPCHK(L, lbmk::launch_adjoint_step(direct, fm, state(j), L->d_adj[ab], L->d_adj[ab ^ 1], gF,
+                                                L->d_taupart, L->d_flags, L->d_force, args, inv_tau2, LA));
+            ab ^= 1;
+            direct = false;
+        }
+    }
+    std::vector<double> parts(nblk);
+    HIPCHK(L, hipMemcpyAsync(parts.data(), L->d_taupart, nblk * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(L, hipStreamSynchronize(L->stream));
+    double s = 0.0;
+    for (double v : parts) s += v;
+    *grad_tau = s;
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+lbm_status run_steps(lbm_lattice* L, int n, bool collide)
+{
+    if (n == 0) return LBM_OK;
+    const lbmk::StepArgs args = step_args(L);
+    const lbmk::Launch LA = launch_of(L);
+    const lbmk::Launch LA4 = L->cpl == 4 ? launch4_of(L) : LA;
+    const int fm = collide ? force_mode(L) : lbmk::FORCE_NONE;
+    const long long R = (long long)L->events.size();
+    if (R > 0 && L->ev_recorded == 0) {
+        HIPCHK(L, hipEventRecord(L->events[0], L->stream));
+        L->ev_recorded = 1;
+    }
+    for (int s = 0; s < n; ++s) {
+        if (L->pattern == LBM_PATTERN_AB && L->cpl == 4) {
+            HIPCHK(L, lbmk::launch_step_ab4(L->storage, collide, fm, L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags,
+                                            L->d_smask, L->d_mmask, L->d_force, args, LA4));
+            L->cur ^= 1;
+        } else if (L->pattern == LBM_PATTERN_AB) {
+            HIPCHK(L, lbmk::launch_step(L->storage, 0, 0, collide, fm, L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags,
+                                        L->d_force, args, LA));
+            L->cur ^= 1;
+        } else {
+            HIPCHK(L, lbmk::launch_step(L->storage, 1, L->parity, collide, fm, L->d_f[0], nullptr, L->d_flags,
+                                        L->d_force, args, LA));
+            L->parity ^= 1;
+        }
+        ++L->steps_done;
+        if (R > 0) {
+            HIPCHK(L, hipEventRecord(L->events[(size_t)(L->ev_recorded % R)], L->stream));
+            ++L->ev_recorded;
+        }
+        if (L->check_interval > 0 && L->steps_done % L->check_interval == 0) {
+            lbm_status st = lbm_check_finite(L);
+            if (st != LBM_OK) return st;
+        }
+    }
+    invalidate(L);
+    return LBM_OK;
+}
+
+}  // namespace
