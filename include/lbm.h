@@ -83,11 +83,12 @@ typedef struct lbm_options {
     int check_interval;   /* > 0: lbm_step checks for non-finite values every
                              this many steps (synchronises the stream) */
     int device;           /* HIP device ordinal; -1 = the current device */
-    int cells_per_lane;   /* AB step: 0 = automatic (4 when nx % 4 == 0),
-                             1 = one point per work-item, 4 = four
-                             consecutive x-points per work-item (needs
-                             nx % 4 == 0 and block_x * block_y <= 256;
-                             block_x then counts work-items) */
+    int cells_per_lane;   /* AB step: points per work-item. 0 = automatic (4
+                             when nx % 4 == 0, else 1); 1; 4; or 8 (16-bit
+                             storage only: 16-byte accesses). 4 and 8 need
+                             nx to be a multiple of them and
+                             block_x * block_y <= 256 (block_x then counts
+                             work-items) */
 } lbm_options;
 
 typedef struct lbm_lattice lbm_lattice;

@@ -75,27 +75,18 @@ struct StBF16 {
     static __device__ __forceinline__ raw_t from_plain(float f, int i) { return (__bf16)(f - weight(i)); }
 };
 
-// Four consecutive elements as one memory access (4-byte or 2-byte aligned:
-// gfx950 global memory accepts element-aligned vector accesses).
-template <class B>
-struct V4 {
-    typedef B t __attribute__((ext_vector_type(4), aligned(sizeof(B))));
+// VW consecutive elements as one memory access (element-aligned: gfx950
+// global memory accepts 4-byte- and 2-byte-aligned vector accesses).
+template <class B, int VW>
+struct Vec {
+    typedef B t __attribute__((ext_vector_type(VW), aligned(sizeof(B))));
 };
-
 template <class B>
-__device__ __forceinline__ typename V4<B>::t ld4(const B* base, uint32_t idx)
-{
-    return *reinterpret_cast<const typename V4<B>::t*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(B));
-}
-template <class B>
-__device__ __forceinline__ void st4(B* base, uint32_t idx, typename V4<B>::t v)
-{
-    *reinterpret_cast<typename V4<B>::t*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(B)) = v;
-}
+using V4 = Vec<B, 4>;
 
-// Element idx of one direction's plane: the byte offset is formed in 32 bits
-// (planes are < 4 GiB), so the load can take the scalar-base + 32-bit
-// vector-offset addressing form.
+// Element idx of an array base: the byte offset is formed in 32 bits (every
+// plane is < 4 GiB), so accesses take the scalar-base + 32-bit vector-offset
+// addressing form.
 template <class T>
 __device__ __forceinline__ T ld(const T* base, uint32_t idx)
 {
@@ -106,6 +97,18 @@ __device__ __forceinline__ void st(T* base, uint32_t idx, T v)
 {
     *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(T)) = v;
 }
+template <int VW, class B>
+__device__ __forceinline__ typename Vec<B, VW>::t ldv(const B* base, uint32_t idx)
+{
+    return *reinterpret_cast<const typename Vec<B, VW>::t*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(B));
+}
+template <int VW, class B>
+__device__ __forceinline__ void stv(B* base, uint32_t idx, typename Vec<B, VW>::t v)
+{
+    *reinterpret_cast<typename Vec<B, VW>::t*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(B)) = v;
+}
+template <class B>
+__device__ __forceinline__ typename V4<B>::t ld4(const B* base, uint32_t idx) { return ldv<4>(base, idx); }
 
 struct Dims {
     int nx, ny, nz;
@@ -113,27 +116,42 @@ struct Dims {
     uint32_t N;     // nx*ny*nz (< 2^30)
 };
 
-// Source index of the pull gather, x - e_i with periodic wrap, for all i.
-// Offsets are added modulo 2^32 (negative offsets wrap back into range).
-__device__ __forceinline__ void pull_sources(const Dims& d, int x, int y, int z, uint32_t c,
-                                             uint32_t src[Q])
+// Population storage: the values of direction i in z-slab z form one plane of
+// nx*ny elements, f[(z*Q + i)*nxy + y*nx + x]. All work-items of a work-group
+// share z, so plane bases are scalar; in-slab offsets are 32-bit.
+template <class T>
+__device__ __forceinline__ T* plane(T* f, const Dims& d, int i, uint32_t z)
 {
+    return f + ((size_t)z * Q + (size_t)i) * d.nxy;
+}
+
+// Slab of the pull source x - e_i given the wrapped z-1 (zm) and z+1 (zp).
+__device__ __forceinline__ uint32_t src_slab(int i, uint32_t z, uint32_t zm, uint32_t zp)
+{
+    return EZ[i] == 1 ? zm : (EZ[i] == -1 ? zp : z);
+}
+
+// In-slab offsets (y'*nx + x') of the pull sources x - e_i, periodic in x, y.
+// Offsets are added modulo 2^32 (negative offsets wrap back into range).
+__device__ __forceinline__ void pull_offsets(const Dims& d, int x, int y, uint32_t o[Q])
+{
+    const uint32_t oc = (uint32_t)y * (uint32_t)d.nx + (uint32_t)x;
     const uint32_t oxm = (x == 0) ? (uint32_t)(d.nx - 1) : 0xffffffffu;              // to x-1
     const uint32_t oxp = (x == d.nx - 1) ? (uint32_t)(1 - d.nx) : 1u;                // to x+1
     const uint32_t oym = (y == 0) ? (uint32_t)(d.ny - 1) * d.nx : (uint32_t)(-d.nx); // to y-1
     const uint32_t oyp = (y == d.ny - 1) ? (uint32_t)(1 - d.ny) * d.nx : (uint32_t)d.nx;
-    const uint32_t ozm = (z == 0) ? (uint32_t)(d.nz - 1) * d.nxy : (uint32_t)0 - d.nxy;
-    const uint32_t ozp = (z == d.nz - 1) ? (uint32_t)(1 - d.nz) * d.nxy : d.nxy;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        uint32_t s = c;
+        uint32_t s = oc;
         // pull from x - e_i: e = +1 reads the minus neighbour
         if (EX[i] == 1) s += oxm; else if (EX[i] == -1) s += oxp;
         if (EY[i] == 1) s += oym; else if (EY[i] == -1) s += oyp;
-        if (EZ[i] == 1) s += ozm; else if (EZ[i] == -1) s += ozp;
-        src[i] = s;
+        o[i] = s;
     }
 }
+
+__device__ __forceinline__ uint32_t wrap_m(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
+__device__ __forceinline__ uint32_t wrap_p(uint32_t v, uint32_t n) { return v == n - 1 ? 0 : v + 1; }
 
 // ---------------------------------------------------------------------------
 // Collision on offsets. In: h_i = p_i - w_i (pre-collision), force F (zero

@@ -31,9 +31,12 @@ hipError_t launch_step(int storage, int pattern, int parity, bool collide, int f
                        void* a, void* b, const uint8_t* flags, const float* ffield,
                        const StepArgs& args, const Launch& L);
 
-// One AB step with four consecutive x-cells per work-item (nx % 4 == 0,
-// at most 256 work-items per work-group; the launch's grid counts quads).
-hipError_t launch_step_ab4(int storage, bool collide, int force_mode, void* a, void* b,
+// One AB step with vw consecutive x-points per work-item: vw = 4 (FP32,
+// 16-byte accesses; or 16-bit storage, 8-byte accesses) or vw = 8 (16-bit
+// storage, 16-byte accesses). Needs nx % vw == 0 and at most 256 work-items
+// per work-group; the launch's grid counts groups of vw points along x.
+bool vector_width_ok(int storage, int vw);
+hipError_t launch_step_abv(int storage, int vw, bool collide, int force_mode, void* a, void* b,
                            const uint8_t* flags, const uint32_t* smask, const uint32_t* mmask,
                            const float* ffield, const StepArgs& args, const Launch& L);
 

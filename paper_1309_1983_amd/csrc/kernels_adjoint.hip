@@ -47,19 +47,20 @@ __global__ __launch_bounds__(1024) void k_adj_seed(const float* __restrict__ f,
     const Dims& d = a.d;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
+    const uint32_t z = blockIdx.z;
     if (x >= d.nx || y >= d.ny) return;
-    const uint32_t c = ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx + (uint32_t)x;
+    const uint32_t o = (uint32_t)y * (uint32_t)d.nx + (uint32_t)x;
+    const uint32_t c = z * d.nxy + o;
     const size_t N = d.N;
     if (flags[c] & TYPE_MASK) {
 #pragma unroll
-        for (int j = 0; j < Q; ++j) aout[j * N + c] = 0.0f;
+        for (int j = 0; j < Q; ++j) st(plane(aout, d, j, z), o, 0.0f);
         gF[c] = 0.0f; gF[N + c] = 0.0f; gF[2 * N + c] = 0.0f;
         return;
     }
     float h[Q];
 #pragma unroll
-    for (int j = 0; j < Q; ++j) h[j] = f[j * N + c] - weight(j);
+    for (int j = 0; j < Q; ++j) h[j] = ld(plane(f, d, j, z), o) - weight(j);
     float Fx, Fy, Fz;
     force_at<FM>(a, ff, c, Fx, Fy, Fz);
     const Macro m = macro_pre<FM != FORCE_NONE>(h, -Fx, -Fy, -Fz);
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(1024) void k_adj_seed(const float* __restrict__ f,
     const float gx = g[c], gy = g[N + c], gz = g[2 * N + c];
     const float ug = fmaf(m.ux, gx, fmaf(m.uy, gy, m.uz * gz));
 #pragma unroll
-    for (int j = 0; j < Q; ++j) aout[j * N + c] = (edot(j, gx, gy, gz) - ug) * ir;
+    for (int j = 0; j < Q; ++j) st(plane(aout, d, j, z), o, (edot(j, gx, gy, gz) - ug) * ir);
     const float h2 = -0.5f * ir;
     gF[c] = gx * h2;
     gF[N + c] = gy * h2;
@@ -87,33 +88,39 @@ __global__ __launch_bounds__(1024) void k_adj_step(const float* __restrict__ s,
     const Dims& d = a.d;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
+    const uint32_t z = blockIdx.z;
     const bool inside = x < d.nx && y < d.ny;
-    const uint32_t c = inside ? ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx + (uint32_t)x : 0u;
+    const uint32_t o = inside ? (uint32_t)y * (uint32_t)d.nx + (uint32_t)x : 0u;
+    const uint32_t c = z * d.nxy + o;
     const uint8_t fl = inside ? flags[c] : (uint8_t)1;
     float tterm = 0.0f;
 
     if (!(fl & TYPE_MASK)) {
         const size_t N = d.N;
-        uint32_t nb[Q];
-        pull_sources(d, x, y, z, c, nb);
+        const uint32_t zm = wrap_m(z, (uint32_t)d.nz), zp = wrap_p(z, (uint32_t)d.nz);
+        uint32_t on[Q];
+        pull_offsets(d, x, y, on);
         float av[Q], h[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            av[i] = DIRECT ? bin[i * N + c] : ld(bin + i * N, nb[OPP[i]]);
-            h[i] = ld(s + i * N, nb[i]);
+            // a_i(x) arrives from b_i(x + e_i); x + e_i is the pull source of opp(i)
+            av[i] = DIRECT ? ld(plane(bin, d, i, z), o)
+                           : ld(plane(bin, d, i, src_slab(OPP[i], z, zm, zp)), on[OPP[i]]);
+            h[i] = ld(plane(s, d, i, src_slab(i, z, zm, zp)), on[i]);
         }
         uint32_t mwmask = 0;
         if (fl & NEAR_WALL) {
 #pragma unroll
             for (int i = 1; i < Q; ++i) {
-                const uint8_t nf = flags[nb[i]];
+                const uint8_t nf = flags[src_slab(i, z, zm, zp) * d.nxy + on[i]];
                 if (nf & TYPE_MASK) {
-                    h[i] = ld(s + OPP[i] * N, c);
+                    h[i] = ld(plane(s, d, OPP[i], z), o);
                     if (nf & MOVING) mwmask |= 1u << i;
                 }
-                // x + e_i = nb[OPP[i]] solid: the adjoint arrives by the bounced link
-                if (!DIRECT && (flags[nb[OPP[i]]] & TYPE_MASK)) av[i] = ld(bin + OPP[i] * N, c);
+                // x + e_i solid: the adjoint arrives by the bounced link
+                const int k = OPP[i];
+                if (!DIRECT && (flags[src_slab(k, z, zm, zp) * d.nxy + on[k]] & TYPE_MASK))
+                    av[i] = ld(plane(bin, d, k, z), o);
             }
         }
 #pragma unroll
@@ -171,7 +178,7 @@ __global__ __launch_bounds__(1024) void k_adj_step(const float* __restrict__ s,
 #pragma unroll
         for (int j = 0; j < Q; ++j) {
             const float bj = fmaf(oneMinus, av[j], base) + (edot(j, Vx, Vy, Vz) - Vu) * ir;
-            bout[j * N + c] = bj;
+            st(plane(bout, d, j, z), o, bj);
         }
         const float Wx = 3.0f * A1x - 3.0f * m.ux * A0 + 9.0f * A2x;
         const float Wy = 3.0f * A1y - 3.0f * m.uy * A0 + 9.0f * A2y;

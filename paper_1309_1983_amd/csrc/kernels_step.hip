@@ -1,15 +1,13 @@
 // Forward kernels for gfx950: the fused pull step (Mawson & Revell, Section 4.2,
 // Algorithm 3) in the two-array (AB) pattern and the single-array (AA)
-// pattern, plus the auxiliary per-cell kernels (initialisation, macroscopic
-// output, state copy in/out, finite check, flag preprocessing, copy probe).
+// pattern, plus the auxiliary per-point kernels (initialisation, macroscopic
+// output, state copy in and out, finite check, flag preprocessing, copy probe).
 //
-// One work-item per lattice point, work-groups x-dominant (Section 6). The
-// population arrays are structure-of-arrays planes (Section 4.1): the 19
-// loads of a wave are each one contiguous 64-element run, shifted by one
-// element for the ten directions with e_x != 0; stores are aligned. The
-// shifted runs straddle one extra cache line that the neighbouring wave of
-// the same row also reads, so the re-read is served from L2 and HBM traffic
-// stays at one read and one write per population.
+// Work-groups are x-dominant (Section 6) and every work-group lies in one
+// z-slab. Populations are stored per (direction, slab) plane (see plane() in
+// d3q19.hpp): the structure-of-arrays coalescing of Section 4.1, with the 19
+// planes of a slab next to each other so that the concurrently running
+// work-groups stream through a compact address window.
 #include "kernels.hpp"
 
 using namespace d3q19;
@@ -56,9 +54,19 @@ __device__ __forceinline__ void decode_collide(const typename St::raw_t raw[Q], 
     bgk_collide<FM != FORCE_NONE>(h, a.omega, a.cF, Fx, Fy, Fz);
 }
 
+#define POINT_PROLOGUE(d)                                                                      \
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;                                       \
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;                                       \
+    const uint32_t z = blockIdx.z;                                                             \
+    if (x >= (d).nx || y >= (d).ny) return;                                                    \
+    const uint32_t o = (uint32_t)y * (uint32_t)(d).nx + (uint32_t)x;                           \
+    const uint32_t c = z * (d).nxy + o;                                                        \
+    const uint32_t zm = wrap_m(z, (uint32_t)(d).nz), zp = wrap_p(z, (uint32_t)(d).nz);
+
 // ---------------------------------------------------------------------------
-// AB pull step: gather from x - e_i in `src`, bounce back at solid
-// neighbours, collide, store aligned into `dst`.
+// AB pull step, one point per work-item: gather from x - e_i in `src`,
+// bounce back at solid neighbours, collide, store into `dst`. Used when the
+// row length is not a multiple of the vector width.
 // ---------------------------------------------------------------------------
 template <class St, int FM, bool COLLIDE>
 __global__ __launch_bounds__(1024) void k_step_ab(const typename St::raw_t* __restrict__ src,
@@ -67,28 +75,24 @@ __global__ __launch_bounds__(1024) void k_step_ab(const typename St::raw_t* __re
                                                   const float* __restrict__ ff, StepArgs a)
 {
     using T = typename St::raw_t;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= a.d.nx || y >= a.d.ny) return;
-    const uint32_t c = ((uint32_t)z * (uint32_t)a.d.ny + (uint32_t)y) * (uint32_t)a.d.nx + (uint32_t)x;
+    const Dims& d = a.d;
+    POINT_PROLOGUE(d)
     const uint8_t fl = flags[c];
     if (fl & TYPE_MASK) return;
 
-    uint32_t nb[Q];
-    pull_sources(a.d, x, y, z, c, nb);
-    const size_t N = a.d.N;
+    uint32_t on[Q];
+    pull_offsets(d, x, y, on);
     T raw[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) raw[i] = ld(src + i * N, nb[i]);
+    for (int i = 0; i < Q; ++i) raw[i] = ld(plane(src, d, i, src_slab(i, z, zm, zp)), on[i]);
 
     uint32_t mwmask = 0;
     if (fl & NEAR_WALL) {
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const uint8_t nf = flags[nb[i]];
+            const uint8_t nf = flags[src_slab(i, z, zm, zp) * d.nxy + on[i]];
             if (nf & TYPE_MASK) {
-                raw[i] = ld(src + OPP[i] * N, c);
+                raw[i] = ld(plane(src, d, OPP[i], z), o);
                 if (nf & MOVING) mwmask |= 1u << i;
             }
         }
@@ -96,28 +100,43 @@ __global__ __launch_bounds__(1024) void k_step_ab(const typename St::raw_t* __re
 
     if (!COLLIDE) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) st(dst + i * N, c, raw[i]);
+        for (int i = 0; i < Q; ++i) st(plane(dst, d, i, z), o, raw[i]);
         return;
     }
     float h[Q];
     decode_collide<St, FM>(raw, mwmask, a, ff, c, h);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st(dst + i * N, c, St::enc(h[i], i));
+    for (int i = 0; i < Q; ++i) st(plane(dst, d, i, z), o, St::enc(h[i], i));
 }
 
 // ---------------------------------------------------------------------------
-// AB pull step, four consecutive x-cells per work-item (nx % 4 == 0).
-// Each direction is one 4-element access: aligned for e_x = 0, shifted by one
-// element for e_x = +-1 (a shifted wave access spans 9 instead of 8 cache
-// lines; the extra line is the neighbouring work-item's and stays in L2).
+// AB pull step, VW consecutive x-points per work-item (nx % VW == 0), one
+// vector access per direction: 16 bytes for FP32 (VW = 4) and for 16-bit
+// storage with VW = 8, 8 bytes for 16-bit storage with VW = 4.
+// Directions with e_x = 0 are aligned accesses; e_x = +-1 are shifted by one
+// element (a shifted wave access spans one extra cache line, which the
+// neighbouring work-item also touches, so HBM traffic does not grow).
 // Row ends are clamped into the row and the periodic wrap element is loaded
-// separately, only when the end cell is fluid. Near-wall cells take the
+// on its own, only when the end point is fluid. Near-wall points take the
 // bounced values s_opp(i)(x) through the precomputed solid-neighbour mask.
-// Solid cells inside a work-item's quad are written as the rest state.
-// Per fluid cell the arithmetic is the same as the one-cell kernel's.
+// Solid points inside a work-item's group are written as the rest state.
+// Per fluid point the arithmetic is the one-point kernel's, bit for bit.
 // ---------------------------------------------------------------------------
-template <class St, int FM, bool COLLIDE>
-__global__ __launch_bounds__(256) void k_step_ab4(const typename St::bits_t* __restrict__ src,
+template <int VW>
+struct FlagWord;
+template <>
+struct FlagWord<4> {
+    typedef uint32_t t;
+    static constexpr uint32_t ones = 0x01010101u;
+};
+template <>
+struct FlagWord<8> {
+    typedef uint64_t t;
+    static constexpr uint64_t ones = 0x0101010101010101ull;
+};
+
+template <class St, int FM, bool COLLIDE, int VW>
+__global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __restrict__ src,
                                                   typename St::bits_t* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
                                                   const uint32_t* __restrict__ smask,
@@ -125,42 +144,42 @@ __global__ __launch_bounds__(256) void k_step_ab4(const typename St::bits_t* __r
                                                   const float* __restrict__ ff, StepArgs a)
 {
     using B = typename St::bits_t;
-    using Vt = typename V4<B>::t;
+    using Vt = typename Vec<B, VW>::t;
+    using FW = typename FlagWord<VW>::t;
+    constexpr FW ONES = FlagWord<VW>::ones;
     const Dims& d = a.d;
-    const int x0 = 4 * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int x0 = VW * (int)(blockIdx.x * blockDim.x + threadIdx.x);
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
+    const uint32_t z = blockIdx.z;
     if (x0 >= d.nx || y >= d.ny) return;
     const uint32_t nx = (uint32_t)d.nx;
-    const uint32_t row = ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * nx;
-    const uint32_t c0 = row + (uint32_t)x0;
-    const uint32_t fl4 = *reinterpret_cast<const uint32_t*>(flags + c0);
-    const uint32_t solid4 = (fl4 | (fl4 >> 1)) & 0x01010101u;   // byte j: cell j solid
-    if (solid4 == 0x01010101u) return;
+    const uint32_t orow = (uint32_t)y * nx;
+    const uint32_t o0 = orow + (uint32_t)x0;
+    const uint32_t c0 = z * d.nxy + o0;
+    const FW flw = *reinterpret_cast<const FW*>(flags + c0);
+    const FW solid = (flw | (flw >> 1)) & ONES;   // byte j: point j solid
+    if (solid == ONES) return;
 
+    const uint32_t zm = wrap_m(z, (uint32_t)d.nz), zp = wrap_p(z, (uint32_t)d.nz);
     const uint32_t oym = (y == 0) ? (uint32_t)(d.ny - 1) * nx : (uint32_t)0 - nx;
     const uint32_t oyp = (y == d.ny - 1) ? (uint32_t)(1 - d.ny) * nx : nx;
-    const uint32_t ozm = (z == 0) ? (uint32_t)(d.nz - 1) * d.nxy : (uint32_t)0 - d.nxy;
-    const uint32_t ozp = (z == d.nz - 1) ? (uint32_t)(1 - d.nz) * d.nxy : d.nxy;
     const bool wl = x0 == 0;
-    const bool wr = (uint32_t)x0 + 4 == nx;
-    const uint32_t xm = wl ? (uint32_t)x0 : (uint32_t)x0 - 1;   // quad start for e_x = +1
-    const uint32_t xp = wr ? (uint32_t)x0 : (uint32_t)x0 + 1;   // quad start for e_x = -1
-    const size_t N = d.N;
+    const bool wr = (uint32_t)x0 + VW == nx;
+    const uint32_t xm = wl ? (uint32_t)x0 : (uint32_t)x0 - 1;   // group start for e_x = +1
+    const uint32_t xp = wr ? (uint32_t)x0 : (uint32_t)x0 + 1;   // group start for e_x = -1
 
     Vt q[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        uint32_t r = row;
+        uint32_t r = orow;
         if (EY[i] == 1) r += oym; else if (EY[i] == -1) r += oyp;
-        if (EZ[i] == 1) r += ozm; else if (EZ[i] == -1) r += ozp;
         const uint32_t xs = EX[i] == 1 ? xm : (EX[i] == -1 ? xp : (uint32_t)x0);
-        q[i] = ld4(src + i * N, r + xs);
+        q[i] = ldv<VW>(plane(src, d, i, src_slab(i, z, zm, zp)), r + xs);
     }
 
     // periodic wrap in x at the two row ends
-    const bool fixl = wl && !(solid4 & 0x1u);
-    const bool fixr = wr && !(solid4 & 0x01000000u);
+    const bool fixl = wl && !(solid & 0x1u);
+    const bool fixr = wr && !((solid >> (8 * (VW - 1))) & 0x1u);
     B wrapv[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) wrapv[i] = B(0);
@@ -168,61 +187,85 @@ __global__ __launch_bounds__(256) void k_step_ab4(const typename St::bits_t* __r
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             if (EX[i] == 0) continue;
-            uint32_t r = row;
+            uint32_t r = orow;
             if (EY[i] == 1) r += oym; else if (EY[i] == -1) r += oyp;
-            if (EZ[i] == 1) r += ozm; else if (EZ[i] == -1) r += ozp;
-            if (EX[i] == 1 && fixl) wrapv[i] = ld(src + i * N, r + nx - 1);
-            if (EX[i] == -1 && fixr) wrapv[i] = ld(src + i * N, r);
+            const B* P = plane(src, d, i, src_slab(i, z, zm, zp));
+            if (EX[i] == 1 && fixl) wrapv[i] = ld(P, r + nx - 1);
+            if (EX[i] == -1 && fixr) wrapv[i] = ld(P, r);
         }
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
+        if (EX[i] == 0) continue;
         const Vt v = q[i];
-        if (EX[i] == 1 && wl) q[i] = Vt{wrapv[i], v.x, v.y, v.z};
-        if (EX[i] == -1 && wr) q[i] = Vt{v.y, v.z, v.w, wrapv[i]};
+        Vt s;
+        if (EX[i] == 1) {
+            s[0] = wrapv[i];
+#pragma unroll
+            for (int k = 1; k < VW; ++k) s[k] = v[k - 1];
+            q[i] = wl ? s : v;
+        } else {
+#pragma unroll
+            for (int k = 0; k < VW - 1; ++k) s[k] = v[k + 1];
+            s[VW - 1] = wrapv[i];
+            q[i] = wr ? s : v;
+        }
     }
 
-    // bounce-back at solid neighbours (cells flagged NEAR_WALL)
-    uint32_t mm[4] = {0u, 0u, 0u, 0u};
-    if (fl4 & 0x04040404u) {
-        const typename V4<uint32_t>::t sm = ld4(smask, c0);
-        if (COLLIDE && (fl4 & 0x08080808u)) {
-            const typename V4<uint32_t>::t m = ld4(mmask, c0);
-            mm[0] = m.x; mm[1] = m.y; mm[2] = m.z; mm[3] = m.w;
+    // bounce-back at solid neighbours (points flagged NEAR_WALL)
+    uint32_t mm[VW];
+#pragma unroll
+    for (int j = 0; j < VW; ++j) mm[j] = 0u;
+    if (flw & (ONES * NEAR_WALL)) {
+        uint32_t sm[VW];
+#pragma unroll
+        for (int g = 0; g < VW / 4; ++g) {
+            const typename V4<uint32_t>::t s4 = ld4(smask, c0 + 4 * g);
+            sm[4 * g] = s4.x; sm[4 * g + 1] = s4.y; sm[4 * g + 2] = s4.z; sm[4 * g + 3] = s4.w;
         }
-        const uint32_t any = sm.x | sm.y | sm.z | sm.w;
+        if (COLLIDE && (flw & (ONES * NEAR_MOVING))) {
+#pragma unroll
+            for (int g = 0; g < VW / 4; ++g) {
+                const typename V4<uint32_t>::t m4 = ld4(mmask, c0 + 4 * g);
+                mm[4 * g] = m4.x; mm[4 * g + 1] = m4.y; mm[4 * g + 2] = m4.z; mm[4 * g + 3] = m4.w;
+            }
+        }
+        uint32_t any = 0;
+#pragma unroll
+        for (int j = 0; j < VW; ++j) any |= sm[j];
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             if ((any >> i) & 1u) {
-                const Vt bb = ld4(src + OPP[i] * N, c0);
+                const Vt bb = ldv<VW>(plane(src, d, OPP[i], z), o0);
                 Vt v = q[i];
-                if ((sm.x >> i) & 1u) v.x = bb.x;
-                if ((sm.y >> i) & 1u) v.y = bb.y;
-                if ((sm.z >> i) & 1u) v.z = bb.z;
-                if ((sm.w >> i) & 1u) v.w = bb.w;
+#pragma unroll
+                for (int j = 0; j < VW; ++j)
+                    if ((sm[j] >> i) & 1u) v[j] = bb[j];
                 q[i] = v;
             }
         }
     }
 
     if (COLLIDE) {
-        float F[3][4];
+        float F[3][VW];
         if (FM == FORCE_FIELD) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const typename V4<float>::t f = ld4(ff + k * N, c0);
-                F[k][0] = f.x; F[k][1] = f.y; F[k][2] = f.z; F[k][3] = f.w;
-            }
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int g = 0; g < VW / 4; ++g) {
+                    const typename V4<float>::t f = ld4(ff + k * (size_t)d.N, c0 + 4 * g);
+                    F[k][4 * g] = f.x; F[k][4 * g + 1] = f.y; F[k][4 * g + 2] = f.z; F[k][4 * g + 3] = f.w;
+                }
         } else {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < VW; ++j) {
                 F[0][j] = FM == FORCE_UNIFORM ? a.Fx : 0.0f;
                 F[1][j] = FM == FORCE_UNIFORM ? a.Fy : 0.0f;
                 F[2][j] = FM == FORCE_UNIFORM ? a.Fz : 0.0f;
             }
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < VW; ++j) {
             float h[Q];
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
@@ -230,13 +273,13 @@ __global__ __launch_bounds__(256) void k_step_ab4(const typename St::bits_t* __r
                 if (i > 0 && ((mm[j] >> i) & 1u)) h[i] = h[i] + a.mw[i];
             }
             bgk_collide<FM != FORCE_NONE>(h, a.omega, a.cF, F[0][j], F[1][j], F[2][j]);
-            const bool sol = (solid4 >> (8 * j)) & 1u;
+            const bool sol = (solid >> (8 * j)) & 1u;
 #pragma unroll
             for (int i = 0; i < Q; ++i) q[i][j] = St::enc_b(sol ? 0.0f : h[i], i);
         }
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st4(dst + i * N, c0, q[i]);
+    for (int i = 0; i < Q; ++i) stv<VW>(plane(dst, d, i, z), o0, q[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -255,44 +298,38 @@ __global__ __launch_bounds__(1024) void k_step_aa0(typename St::raw_t* f,
                                                    const float* __restrict__ ff, StepArgs a)
 {
     using T = typename St::raw_t;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= a.d.nx || y >= a.d.ny) return;
-    const uint32_t c = ((uint32_t)z * (uint32_t)a.d.ny + (uint32_t)y) * (uint32_t)a.d.nx + (uint32_t)x;
+    const Dims& d = a.d;
+    POINT_PROLOGUE(d)
     const uint8_t fl = flags[c];
     if (fl & TYPE_MASK) return;
 
-    uint32_t nb[Q];
-    pull_sources(a.d, x, y, z, c, nb);
-    const size_t N = a.d.N;
+    uint32_t on[Q];
+    pull_offsets(d, x, y, on);
     T raw[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) raw[i] = ld(f + i * N, nb[i]);
+    for (int i = 0; i < Q; ++i) raw[i] = ld(plane(f, d, i, src_slab(i, z, zm, zp)), on[i]);
 
     uint32_t solid = 0, mwmask = 0;
     if (fl & NEAR_WALL) {
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const uint8_t nf = flags[nb[i]];
+            const uint8_t nf = flags[src_slab(i, z, zm, zp) * d.nxy + on[i]];
             if (nf & TYPE_MASK) {
                 solid |= 1u << i;
-                raw[i] = ld(f + OPP[i] * N, c);
+                raw[i] = ld(plane(f, d, OPP[i], z), o);
                 if (nf & MOVING) mwmask |= 1u << i;
             }
         }
     }
 
     float h[Q];
-    if (COLLIDE) {
-        decode_collide<St, FM>(raw, mwmask, a, ff, c, h);
-    }
+    if (COLLIDE) decode_collide<St, FM>(raw, mwmask, a, ff, c, h);
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-        const int o = OPP[j];
+        const int k = OPP[j];
         const T v = COLLIDE ? St::enc(h[j], j) : raw[j];
-        if ((solid >> o) & 1u) st(f + j * N, c, v);
-        else st(f + o * N, nb[o], v);
+        if ((solid >> k) & 1u) st(plane(f, d, j, z), o, v);
+        else st(plane(f, d, k, src_slab(k, z, zm, zp)), on[k], v);
     }
 }
 
@@ -302,80 +339,71 @@ __global__ __launch_bounds__(1024) void k_step_aa1(typename St::raw_t* f,
                                                    const float* __restrict__ ff, StepArgs a)
 {
     using T = typename St::raw_t;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= a.d.nx || y >= a.d.ny) return;
-    const uint32_t c = ((uint32_t)z * (uint32_t)a.d.ny + (uint32_t)y) * (uint32_t)a.d.nx + (uint32_t)x;
+    const Dims& d = a.d;
+    POINT_PROLOGUE(d)
     const uint8_t fl = flags[c];
     if (fl & TYPE_MASK) return;
 
-    const size_t N = a.d.N;
     T raw[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) raw[i] = ld(f + OPP[i] * N, c);
+    for (int i = 0; i < Q; ++i) raw[i] = ld(plane(f, d, OPP[i], z), o);
 
     uint32_t mwmask = 0;
-    if (COLLIDE && (fl & NEAR_WALL)) {
-        uint32_t nb[Q];
-        pull_sources(a.d, x, y, z, c, nb);
+    if (COLLIDE && (fl & NEAR_MOVING)) {
+        uint32_t on[Q];
+        pull_offsets(d, x, y, on);
 #pragma unroll
         for (int i = 1; i < Q; ++i)
-            if ((flags[nb[i]] & TYPE_MASK) == MOVING) mwmask |= 1u << i;
+            if ((flags[src_slab(i, z, zm, zp) * d.nxy + on[i]] & TYPE_MASK) == MOVING) mwmask |= 1u << i;
     }
     if (!COLLIDE) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) st(f + i * N, c, raw[i]);
+        for (int i = 0; i < Q; ++i) st(plane(f, d, i, z), o, raw[i]);
         return;
     }
     float h[Q];
     decode_collide<St, FM>(raw, mwmask, a, ff, c, h);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st(f + i * N, c, St::enc(h[i], i));
+    for (int i = 0; i < Q; ++i) st(plane(f, d, i, z), o, St::enc(h[i], i));
 }
 
 // ---------------------------------------------------------------------------
-// Stored state of one cell in natural order (s_j(x), j = 0..18), for either
+// Stored state of one point in natural order (s_j(x), j = 0..18), for either
 // layout. Layout 1 (AA after an odd number of steps): s_j(x) is at
 // [opp(j)][x + e_j] when x + e_j is fluid, else at [j][x].
 // ---------------------------------------------------------------------------
 template <class St, int LAYOUT>
 __device__ __forceinline__ void load_state(const typename St::raw_t* __restrict__ f,
                                            const uint8_t* __restrict__ flags, const Dims& d, int x,
-                                           int y, int z, uint32_t c, uint8_t fl,
+                                           int y, uint32_t z, uint32_t o, uint8_t fl,
                                            typename St::raw_t raw[Q])
 {
-    const size_t N = d.N;
     if (LAYOUT == 0 || (fl & TYPE_MASK)) {
 #pragma unroll
-        for (int j = 0; j < Q; ++j) raw[j] = ld(f + j * N, c);
+        for (int j = 0; j < Q; ++j) raw[j] = ld(plane(f, d, j, z), o);
         return;
     }
-    uint32_t nb[Q];
-    pull_sources(d, x, y, z, c, nb);
+    const uint32_t zm = wrap_m(z, (uint32_t)d.nz), zp = wrap_p(z, (uint32_t)d.nz);
+    uint32_t on[Q];
+    pull_offsets(d, x, y, on);
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-        const int o = OPP[j];
-        const bool wall = (fl & NEAR_WALL) && (flags[nb[o]] & TYPE_MASK);
-        raw[j] = wall ? ld(f + j * N, c) : ld(f + o * N, nb[o]);
+        const int k = OPP[j];
+        const uint32_t zk = src_slab(k, z, zm, zp);
+        const bool wall = (fl & NEAR_WALL) && (flags[zk * d.nxy + on[k]] & TYPE_MASK);
+        raw[j] = wall ? ld(plane(f, d, j, z), o) : ld(plane(f, d, k, zk), on[k]);
     }
 }
-
-#define CELL_PROLOGUE                                                                          \
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;                                       \
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;                                       \
-    const int z = blockIdx.z;                                                                  \
-    if (x >= d.nx || y >= d.ny) return;                                                        \
-    const uint32_t c = ((uint32_t)z * (uint32_t)d.ny + (uint32_t)y) * (uint32_t)d.nx + (uint32_t)x;
 
 template <class St, int LAYOUT>
 __global__ __launch_bounds__(1024) void k_get(const typename St::raw_t* __restrict__ f,
                                               const uint8_t* __restrict__ flags,
                                               float* __restrict__ out, Dims d)
 {
-    CELL_PROLOGUE
+    POINT_PROLOGUE(d)
+    (void)zm; (void)zp;
     typename St::raw_t raw[Q];
-    load_state<St, LAYOUT>(f, flags, d, x, y, z, c, flags[c], raw);
+    load_state<St, LAYOUT>(f, flags, d, x, y, z, o, flags[c], raw);
 #pragma unroll
     for (int j = 0; j < Q; ++j) out[(size_t)j * d.N + c] = St::plain(raw[j], j);
 }
@@ -384,9 +412,10 @@ template <class St>
 __global__ __launch_bounds__(1024) void k_set(typename St::raw_t* __restrict__ f,
                                               const float* __restrict__ in, Dims d)
 {
-    CELL_PROLOGUE
+    POINT_PROLOGUE(d)
+    (void)zm; (void)zp;
 #pragma unroll
-    for (int j = 0; j < Q; ++j) st(f + j * (size_t)d.N, c, St::from_plain(in[(size_t)j * d.N + c], j));
+    for (int j = 0; j < Q; ++j) st(plane(f, d, j, z), o, St::from_plain(in[(size_t)j * d.N + c], j));
 }
 
 template <class St>
@@ -394,7 +423,8 @@ __global__ __launch_bounds__(1024) void k_init_eq(typename St::raw_t* __restrict
                                                   const float* __restrict__ rho,
                                                   const float* __restrict__ u, Dims d)
 {
-    CELL_PROLOGUE
+    POINT_PROLOGUE(d)
+    (void)zm; (void)zp;
     Macro m;
     m.rho = rho ? rho[c] : 1.0f;
     m.drho = m.rho - 1.0f;
@@ -403,7 +433,7 @@ __global__ __launch_bounds__(1024) void k_init_eq(typename St::raw_t* __restrict
     m.uz = u ? u[2 * (size_t)d.N + c] : 0.0f;
     const float A = eq_A(m);
 #pragma unroll
-    for (int j = 0; j < Q; ++j) st(f + j * (size_t)d.N, c, St::enc(heq(j, m, A), j));
+    for (int j = 0; j < Q; ++j) st(plane(f, d, j, z), o, St::enc(heq(j, m, A), j));
 }
 
 template <class St, int LAYOUT, int FM>
@@ -414,7 +444,8 @@ __global__ __launch_bounds__(1024) void k_macros(const typename St::raw_t* __res
                                                  StepArgs a)
 {
     const Dims& d = a.d;
-    CELL_PROLOGUE
+    POINT_PROLOGUE(d)
+    (void)zm; (void)zp;
     const uint8_t fl = flags[c];
     const size_t N = d.N;
     if (fl & TYPE_MASK) {
@@ -423,7 +454,7 @@ __global__ __launch_bounds__(1024) void k_macros(const typename St::raw_t* __res
         return;
     }
     typename St::raw_t raw[Q];
-    load_state<St, LAYOUT>(f, flags, d, x, y, z, c, fl, raw);
+    load_state<St, LAYOUT>(f, flags, d, x, y, z, o, fl, raw);
     float h[Q];
 #pragma unroll
     for (int j = 0; j < Q; ++j) h[j] = St::off(raw[j], j);
@@ -440,11 +471,12 @@ __global__ __launch_bounds__(1024) void k_check_finite(const typename St::raw_t*
                                                        const uint8_t* __restrict__ flags,
                                                        int* flag, Dims d)
 {
-    CELL_PROLOGUE
+    POINT_PROLOGUE(d)
+    (void)zm; (void)zp;
     const uint8_t fl = flags[c];
     if (fl & TYPE_MASK) return;
     typename St::raw_t raw[Q];
-    load_state<St, LAYOUT>(f, flags, d, x, y, z, c, fl, raw);
+    load_state<St, LAYOUT>(f, flags, d, x, y, z, o, fl, raw);
     bool ok = true;
 #pragma unroll
     for (int j = 0; j < Q; ++j) ok = ok && isfinite(St::off(raw[j], j));
@@ -456,16 +488,16 @@ __global__ __launch_bounds__(1024) void k_mark_near_wall(const uint8_t* __restri
                                                          uint32_t* __restrict__ smask,
                                                          uint32_t* __restrict__ mmask, Dims d)
 {
-    CELL_PROLOGUE
+    POINT_PROLOGUE(d)
     const uint8_t fl = in[c] & TYPE_MASK;
     uint8_t r = fl;
     uint32_t sm = 0, mm = 0;
     if (fl == 0) {
-        uint32_t nb[Q];
-        pull_sources(d, x, y, z, c, nb);
+        uint32_t on[Q];
+        pull_offsets(d, x, y, on);
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const uint8_t t = in[nb[i]] & TYPE_MASK;
+            const uint8_t t = in[src_slab(i, z, zm, zp) * d.nxy + on[i]] & TYPE_MASK;
             if (t) sm |= 1u << i;
             if (t == MOVING) mm |= 1u << i;
         }
@@ -529,42 +561,6 @@ static hipError_t step_st(int pattern, int parity, bool collide, int fm, void* a
     }
 }
 
-template <class St, int FM>
-static hipError_t step4_fm(bool collide, void* a, void* b, const uint8_t* flags, const uint32_t* sm,
-                           const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L)
-{
-    using B = typename St::bits_t;
-    const B* A = static_cast<const B*>(a);
-    B* Bp = static_cast<B*>(b);
-    if (collide)
-        hipLaunchKernelGGL((k_step_ab4<St, FM, true>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args);
-    else
-        hipLaunchKernelGGL((k_step_ab4<St, FORCE_NONE, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args);
-    return hipGetLastError();
-}
-
-template <class St>
-static hipError_t step4_st(bool collide, int fm, void* a, void* b, const uint8_t* flags, const uint32_t* sm,
-                           const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L)
-{
-    switch (fm) {
-    case FORCE_UNIFORM: return step4_fm<St, FORCE_UNIFORM>(collide, a, b, flags, sm, mm, ff, args, L);
-    case FORCE_FIELD: return step4_fm<St, FORCE_FIELD>(collide, a, b, flags, sm, mm, ff, args, L);
-    default: return step4_fm<St, FORCE_NONE>(collide, a, b, flags, sm, mm, ff, args, L);
-    }
-}
-
-hipError_t launch_step_ab4(int storage, bool collide, int force_mode, void* a, void* b, const uint8_t* flags,
-                           const uint32_t* smask, const uint32_t* mmask, const float* ffield,
-                           const StepArgs& args, const Launch& L)
-{
-    switch (storage) {
-    case 1: return step4_st<StF16>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
-    case 2: return step4_st<StBF16>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
-    default: return step4_st<StF32>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
-    }
-}
-
 hipError_t launch_step(int storage, int pattern, int parity, bool collide, int force_mode, void* a,
                        void* b, const uint8_t* flags, const float* ffield, const StepArgs& args,
                        const Launch& L)
@@ -573,6 +569,47 @@ hipError_t launch_step(int storage, int pattern, int parity, bool collide, int f
     case 1: return step_st<StF16>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L);
     case 2: return step_st<StBF16>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L);
     default: return step_st<StF32>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L);
+    }
+}
+
+template <class St, int FM, int VW>
+static hipError_t stepv_fm(bool collide, void* a, void* b, const uint8_t* flags, const uint32_t* sm,
+                           const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L)
+{
+    using B = typename St::bits_t;
+    const B* A = static_cast<const B*>(a);
+    B* Bp = static_cast<B*>(b);
+    if (collide)
+        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args);
+    else
+        hipLaunchKernelGGL((k_step_abv<St, FORCE_NONE, false, VW>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args);
+    return hipGetLastError();
+}
+
+template <class St, int VW>
+static hipError_t stepv_st(bool collide, int fm, void* a, void* b, const uint8_t* flags, const uint32_t* sm,
+                           const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L)
+{
+    switch (fm) {
+    case FORCE_UNIFORM: return stepv_fm<St, FORCE_UNIFORM, VW>(collide, a, b, flags, sm, mm, ff, args, L);
+    case FORCE_FIELD: return stepv_fm<St, FORCE_FIELD, VW>(collide, a, b, flags, sm, mm, ff, args, L);
+    default: return stepv_fm<St, FORCE_NONE, VW>(collide, a, b, flags, sm, mm, ff, args, L);
+    }
+}
+
+bool vector_width_ok(int storage, int vw) { return vw == 4 || (vw == 8 && storage != 0); }
+
+hipError_t launch_step_abv(int storage, int vw, bool collide, int force_mode, void* a, void* b,
+                           const uint8_t* flags, const uint32_t* smask, const uint32_t* mmask,
+                           const float* ffield, const StepArgs& args, const Launch& L)
+{
+    switch (storage * 16 + vw) {
+    case 1 * 16 + 8: return stepv_st<StF16, 8>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
+    case 1 * 16 + 4: return stepv_st<StF16, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
+    case 2 * 16 + 8: return stepv_st<StBF16, 8>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
+    case 2 * 16 + 4: return stepv_st<StBF16, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
+    case 0 * 16 + 4: return stepv_st<StF32, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
+    default: return hipErrorInvalidValue;
     }
 }
 

@@ -66,8 +66,8 @@ struct lbm_lattice {
     uint32_t* d_smask = nullptr;   // solid-neighbour bits per cell
     uint32_t* d_mmask = nullptr;   // moving-wall-neighbour bits per cell
     int* d_check = nullptr;
-    int cpl = 1;                   // cells per work-item of the AB step
-    int bx4 = 64, by4 = 4;         // work-group of the four-cell kernel
+    int cpl = 1;                   // points per work-item of the AB step (1 or the vector width)
+    int bx4 = 64, by4 = 1;         // work-group of the vector kernel
 
     bool sticky = false;
     long long steps_done = 0;
@@ -156,11 +156,11 @@ lbmk::StepArgs step_args(const lbm_lattice* L)
 
 lbmk::Launch launch_of(const lbm_lattice* L) { return lbmk::make_launch(L->dims, L->bx, L->by, L->stream); }
 
-// Only valid when the lattice uses the four-cell kernel (cpl == 4).
+// Only valid when the lattice uses the vector kernel (cpl > 1).
 lbmk::Launch launch4_of(const lbm_lattice* L)
 {
     d3q19::Dims q = L->dims;
-    q.nx = L->nx / 4;   // the grid counts quads along x
+    q.nx = L->nx / L->cpl;   // the grid counts groups of cpl points along x
     return lbmk::make_launch(q, L->bx4, L->by4, L->stream);
 }
 
@@ -265,24 +265,28 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
     if (bx <= 0 || by <= 0 || bx * by > 1024) return fail(LBM_ERR_INVALID, "bad block shape %dx%d", bx, by);
     if ((ny + by - 1) / by > 65535) return fail(LBM_ERR_INVALID, "ny/block_y must be <= 65535 work-groups");
     if (opt.timing_capacity < 0 || opt.check_interval < 0) return fail(LBM_ERR_INVALID, "negative timing/check option");
-    if (opt.cells_per_lane != 0 && opt.cells_per_lane != 1 && opt.cells_per_lane != 4)
-        return fail(LBM_ERR_INVALID, "cells_per_lane must be 0, 1 or 4 (got %d)", opt.cells_per_lane);
+    if (opt.cells_per_lane != 0 && opt.cells_per_lane != 1 && !lbmk::vector_width_ok(opt.storage, opt.cells_per_lane))
+        return fail(LBM_ERR_INVALID, "cells_per_lane must be 0, 1, 4%s (got %d)",
+                    opt.storage == LBM_STORAGE_F32 ? "" : " or 8", opt.cells_per_lane);
+    // default vector width: 16-byte accesses for FP32, 8-byte for 16-bit storage
+    const int vw = opt.cells_per_lane > 1 ? opt.cells_per_lane : 4;
     int cpl = 1, bx4 = 0, by4 = 0;
-    if (opt.pattern == LBM_PATTERN_AB && nx % 4 == 0 && opt.cells_per_lane != 1) {
+    if (opt.pattern == LBM_PATTERN_AB && nx % vw == 0 && opt.cells_per_lane != 1) {
         if (opt.block_x == 0 && opt.block_y == 0) {
-            // one wave per work-group along x (a whole 256-point row when nx = 256):
-            // the fastest shape measured at 256^3 on MI355X
-            bx4 = std::min(nx / 4, 64);
+            // one wave per work-group along x (a whole 256-point row when
+            // nx = 256 and vw = 4): the fastest shape measured at 256^3 on MI355X
+            bx4 = std::min(nx / vw, 64);
             by4 = std::max(1, 64 / bx4);
-            cpl = 4;
+            cpl = vw;
         } else if (bx * by <= 256) {
             bx4 = bx; by4 = by;
-            cpl = 4;
+            cpl = vw;
         }
     }
-    if (opt.cells_per_lane == 4 && cpl != 4)
-        return fail(LBM_ERR_INVALID, "cells_per_lane = 4 needs the AB pattern, nx %% 4 == 0 and <= 256 work-items per group");
-    if (cpl == 4 && (ny + by4 - 1) / by4 > 65535) return fail(LBM_ERR_INVALID, "ny/block_y must be <= 65535 work-groups");
+    if (opt.cells_per_lane > 1 && cpl != opt.cells_per_lane)
+        return fail(LBM_ERR_INVALID, "cells_per_lane = %d needs the AB pattern, nx %% %d == 0 and <= 256 work-items per group",
+                    vw, vw);
+    if (cpl > 1 && (ny + by4 - 1) / by4 > 65535) return fail(LBM_ERR_INVALID, "ny/block_y must be <= 65535 work-groups");
     if (flags_host) {
         for (unsigned long long c = 0; c < N; ++c)
             if (flags_host[c] > 2) return fail(LBM_ERR_INVALID, "flag value %u at point %llu (allowed 0, 1, 2)", flags_host[c], c);
@@ -310,7 +314,7 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
     L->timing_cap = opt.timing_capacity;
     L->check_interval = opt.check_interval;
     L->cpl = cpl;
-    if (cpl == 4) { L->bx4 = bx4; L->by4 = by4; }
+    if (cpl > 1) { L->bx4 = bx4; L->by4 = by4; }
 
     lbm_status st = LBM_OK;
     const size_t fbytes = (size_t)Q * L->N * storage_bytes(L->storage);
@@ -651,8 +655,8 @@ lbm_status lbm_adjoint(lbm_lattice* L, const float* g, float* gF, double* grad_t
         // recompute s^{t0+1} .. s^{t0+len-1} into the segment store
         auto state = [&](int j) -> float* { return j == 0 ? L->ckpt[k] : L->d_seg + (size_t)(j - 1) * Q * L->N; };
         for (int j = 1; j < len; ++j) {
-            if (L->cpl == 4)
-                HIPCHK(L, lbmk::launch_step_ab4(LBM_STORAGE_F32, true, fm, state(j - 1), state(j), L->d_flags,
+            if (L->cpl > 1)
+                HIPCHK(L, lbmk::launch_step_abv(LBM_STORAGE_F32, L->cpl, true, fm, state(j - 1), state(j), L->d_flags,
                                                 L->d_smask, L->d_mmask, L->d_force, args, launch4_of(L)));
             else
                 HIPCHK(L, lbmk::launch_step(LBM_STORAGE_F32, LBM_PATTERN_AB, 0, true, fm, state(j - 1), state(j),
@@ -683,7 +687,7 @@ lbm_status run_steps(lbm_lattice* L, int n, bool collide)
     if (n == 0) return LBM_OK;
     const lbmk::StepArgs args = step_args(L);
     const lbmk::Launch LA = launch_of(L);
-    const lbmk::Launch LA4 = L->cpl == 4 ? launch4_of(L) : LA;
+    const lbmk::Launch LA4 = L->cpl > 1 ? launch4_of(L) : LA;
     const int fm = collide ? force_mode(L) : lbmk::FORCE_NONE;
     const long long R = (long long)L->events.size();
     if (R > 0 && L->ev_recorded == 0) {
@@ -691,8 +695,8 @@ lbm_status run_steps(lbm_lattice* L, int n, bool collide)
         L->ev_recorded = 1;
     }
     for (int s = 0; s < n; ++s) {
-        if (L->pattern == LBM_PATTERN_AB && L->cpl == 4) {
-            HIPCHK(L, lbmk::launch_step_ab4(L->storage, collide, fm, L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags,
+        if (L->pattern == LBM_PATTERN_AB && L->cpl > 1) {
+            HIPCHK(L, lbmk::launch_step_abv(L->storage, L->cpl, collide, fm, L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags,
                                             L->d_smask, L->d_mmask, L->d_force, args, LA4));
             L->cur ^= 1;
         } else if (L->pattern == LBM_PATTERN_AB) {

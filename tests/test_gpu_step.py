@@ -210,16 +210,20 @@ FOUR_CELL_CASES = [
     ((64, 9, 7), 0.0, 0.0, (1e-5, -2e-5, 3e-6), False),   # periodic in x: row-end wrap
     ((4, 5, 6), 0.15, 0.05, None, False),       # one quad per row: both row ends in one work-item
     ((256, 3, 2), 0.3, 0.1, (0, 0, 1e-5), False),
+    ((8, 6, 5), 0.1, 0.05, None, True),         # one 8-point group per row
+    ((40, 7, 3), 0.0, 0.0, None, True),         # periodic in x, five 8-point groups per row
 ]
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage,width", [("f32", 4), ("f16", 4), ("bf16", 4), ("f16", 8), ("bf16", 8)])
 @pytest.mark.parametrize("case", range(len(FOUR_CELL_CASES)))
-def test_four_cell_kernel_equals_one_cell_kernel(storage, case):
-    """The four-points-per-work-item AB kernel performs the same per-point
+def test_vector_kernel_equals_one_point_kernel(storage, width, case):
+    """The several-points-per-work-item AB kernel performs the same per-point
     arithmetic as the one-point kernel: fluid results agree bit for bit,
-    including the periodic wrap at row ends and solid points inside a quad."""
+    including the periodic wrap at row ends and solid points inside a group."""
     shape, solid, moving, force, field = FOUR_CELL_CASES[case]
+    if shape[0] % width:
+        pytest.skip(f"nx = {shape[0]} is not a multiple of {width}")
     N = int(np.prod(shape))
     flags = W.random_flags(N, seed=40 + case, solid_fraction=solid, moving_fraction=moving)
     ff = W.random_force_field(N, 41, 1e-4).astype(np.float32) if field else None
@@ -227,12 +231,12 @@ def test_four_cell_kernel_equals_one_cell_kernel(storage, case):
     kw = dict(flags=flags, uw=(0.05, -0.02, 0.03), force=force, force_field=ff, storage=storage)
     for steps in (1, 3):
         one = _gpu_run(shape, 0.8, s0, steps, cells_per_lane=1, **kw)
-        four = _gpu_run(shape, 0.8, s0, steps, cells_per_lane=4, **kw)
+        vec = _gpu_run(shape, 0.8, s0, steps, cells_per_lane=width, **kw)
         fl = flags == 0
-        np.testing.assert_array_equal(four[:, fl], one[:, fl], err_msg=f"{storage} {shape} {steps}")
+        np.testing.assert_array_equal(vec[:, fl], one[:, fl], err_msg=f"{storage} {shape} {steps}")
     stream1 = _gpu_run(shape, 0.8, s0, 2, stream_only=True, cells_per_lane=1, **kw)
-    stream4 = _gpu_run(shape, 0.8, s0, 2, stream_only=True, cells_per_lane=4, **kw)
-    np.testing.assert_array_equal(stream4[:, flags == 0], stream1[:, flags == 0])
+    streamv = _gpu_run(shape, 0.8, s0, 2, stream_only=True, cells_per_lane=width, **kw)
+    np.testing.assert_array_equal(streamv[:, flags == 0], stream1[:, flags == 0])
 
 
 @pytest.mark.parametrize("block", [(8, 1), (16, 4), (64, 4), (64, 1), (32, 8), (3, 5)])
