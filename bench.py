@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, decimal GB/s
 BYTES_PER_POINT = {"f32": 152, "f16": 76, "bf16": 76}   # 19 loads + 19 stores
+MACROS_BYTES = 16   # rho and u stored every step (Section 4.1: 152 -> 168 B)
 ADJOINT_BYTES_PER_POINT = 152 + 264  # recompute step + reverse step (see DESIGN)
 
 
@@ -75,11 +76,12 @@ def time_steps(lat, steps, torch):
     return e0.elapsed_time(e1) / steps
 
 
-def cavity_lattice(n, storage, pattern, tau, lid, block=None):
+def cavity_lattice(n, storage, pattern, tau, lid, block=None, cells_per_lane=0):
     import workloads as W
     from paper_1309_1983_amd import Lattice
     flags = W.cavity_flags(n, n, n)
-    lat = Lattice(n, n, n, tau, flags=flags, storage=storage, pattern=pattern, block=block)
+    lat = Lattice(n, n, n, tau, flags=flags, storage=storage, pattern=pattern, block=block,
+                  cells_per_lane=cells_per_lane)
     lat.set_wall_velocity(lid)
     return lat
 
@@ -272,17 +274,44 @@ def main():
         extra["copy_ceiling_gbs"] = round(cc, 1)
         line["roofline"]["frac_of_copy_ceiling"] = round(achieved / cc, 4)
         log(f"copy ceiling {cc:.0f} GB/s")
-        for storage, pattern in (("f16", "ab"), ("bf16", "ab"), ("f16", "aa"), ("f32", "aa")):
-            lat = cavity_lattice(n, storage, pattern, tau, lid)
+        for storage, pattern, cpl in (("f16", "ab", 0), ("bf16", "ab", 0), ("f16", "ab", 8),
+                                      ("bf16", "ab", 8), ("f16", "aa", 0), ("bf16", "aa", 0),
+                                      ("f32", "aa", 0)):
+            lat = cavity_lattice(n, storage, pattern, tau, lid, cells_per_lane=cpl)
             lat.step(args.warmup)
             m = time_steps(lat, args.steps, torch)
             lat.close()
             bpp = BYTES_PER_POINT[storage]
             gbs = bpp * N / (m * 1e-3) / 1e9
-            extra[f"{storage}_{pattern}"] = {"mlups": round(N / m / 1e3, 1), "ms_per_step": round(m, 5),
+            key = f"{storage}_{pattern}" + (f"_w{cpl}" if cpl else "")
+            extra[key] = {"mlups": round(N / m / 1e3, 1), "ms_per_step": round(m, 5),
+                          "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                          "bytes_per_point": bpp}
+            log(f"{key}: {m:.4f} ms/step, {N / m / 1e3:.0f} MLUPS, {gbs:.0f} GB/s")
+        # the step with rho and u stored every step (four extra stores per point)
+        lat = cavity_lattice(n, "f32", "ab", tau, lid)
+        lat.step(args.warmup)
+        rho = torch.empty(N, device="cuda")
+        u = torch.empty(3, N, device="cuda")
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        from paper_1309_1983_amd import _abi
+        import ctypes
+        for _ in range(args.steps):
+            _abi.call("lbm_step_macros", lat._h, 1, ctypes.c_void_p(rho.data_ptr()),
+                      ctypes.c_void_p(u.data_ptr()))
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        m = e0.elapsed_time(e1) / args.steps
+        lat.close()
+        bpp = BYTES_PER_POINT["f32"] + MACROS_BYTES
+        gbs = bpp * N / (m * 1e-3) / 1e9
+        extra["f32_ab_macros_every_step"] = {"mlups": round(N / m / 1e3, 1), "ms_per_step": round(m, 5),
                                              "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                                              "bytes_per_point": bpp}
-            log(f"{storage} {pattern}: {m:.4f} ms/step, {N / m / 1e3:.0f} MLUPS, {gbs:.0f} GB/s")
+        log(f"f32_ab with rho,u every step: {m:.4f} ms/step, {N / m / 1e3:.0f} MLUPS, {gbs:.0f} GB/s")
         try:
             ar, gb = adjoint_rate(torch, n, T=200, K=50, tau=0.7)
             extra["adjoint"] = {"mlups": round(ar, 1), "T": 200, "K": 50, "device_gb": round(gb, 1),

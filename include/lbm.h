@@ -151,6 +151,15 @@ lbm_status lbm_init_equilibrium(lbm_lattice* lat, const float* rho_dev, const fl
  * LBM_ERR_NONFINITE when a due check (check_interval) finds NaN/Inf. */
 lbm_status lbm_step(lbm_lattice* lat, int n);
 
+/* n >= 1 steps as lbm_step, where the last one also writes its in-step
+ * rho and u = (sum_i e_i p_i + F/2)/rho (Eqs. (6)-(7)) into rho_dev [N] and
+ * u_dev [3][N] (0 at solid points): the four extra stores per point of the
+ * paper's macroscopic-output variant (Section 4.1), fused into the step
+ * instead of a separate pass. These equal lbm_macros of the resulting state
+ * up to rounding. In the AA pattern the output is a separate pass after the
+ * steps. Errors: as lbm_step; LBM_ERR_INVALID for n < 1 or a NULL output. */
+lbm_status lbm_step_macros(lbm_lattice* lat, int n, float* rho_dev, float* u_dev);
+
 /* Writes rho = sum_i s_i and u = (sum_i e_i s_i - F/2)/rho (Eqs. (6)-(7) on
  * the post-collision state) into rho_dev [N] and u_dev [3][N]; solid points
  * get rho = 0, u = 0. Either pointer may be NULL to skip it, not both. */

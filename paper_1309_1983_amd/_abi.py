@@ -18,7 +18,7 @@ PATTERN = {"ab": 0, "aa": 1}
 EXPORTS = [
     "lbm_options_default", "lbm_create", "lbm_create_ex", "lbm_destroy", "lbm_get_info",
     "lbm_set_stream", "lbm_set_tau", "lbm_set_wall_velocity", "lbm_set_force_uniform",
-    "lbm_set_force_field", "lbm_init_equilibrium", "lbm_step", "lbm_macros",
+    "lbm_set_force_field", "lbm_init_equilibrium", "lbm_step", "lbm_step_macros", "lbm_macros",
     "lbm_get_populations", "lbm_set_populations", "lbm_debug_stream_only",
     "lbm_forward_checkpointed", "lbm_adjoint", "lbm_check_finite", "lbm_step_times", "lbm_sync",
     "lbm_device_bytes", "lbm_status_string", "lbm_last_error", "lbm_copy_f32",
@@ -78,6 +78,7 @@ def lib():
         "lbm_set_force_field": (c_int, [vp, fp]),
         "lbm_init_equilibrium": (c_int, [vp, fp, fp]),
         "lbm_step": (c_int, [vp, c_int]),
+        "lbm_step_macros": (c_int, [vp, c_int, fp, fp]),
         "lbm_macros": (c_int, [vp, fp, fp]),
         "lbm_get_populations": (c_int, [vp, fp]),
         "lbm_set_populations": (c_int, [vp, fp]),

@@ -153,6 +153,127 @@ __device__ __forceinline__ void pull_offsets(const Dims& d, int x, int y, uint32
 __device__ __forceinline__ uint32_t wrap_m(uint32_t v, uint32_t n) { return v == 0 ? n - 1 : v - 1; }
 __device__ __forceinline__ uint32_t wrap_p(uint32_t v, uint32_t n) { return v == n - 1 ? 0 : v + 1; }
 
+// VW consecutive 32-bit words at base[idx] (idx a multiple of min(VW, 4)).
+template <int VW>
+__device__ __forceinline__ void load_words(const uint32_t* __restrict__ base, uint32_t idx, uint32_t w[VW])
+{
+    constexpr int G = VW < 4 ? VW : 4;
+#pragma unroll
+    for (int g = 0; g < VW / G; ++g) {
+        const typename Vec<uint32_t, G>::t v = ldv<G>(base, idx + G * g);
+#pragma unroll
+        for (int k = 0; k < G; ++k) w[G * g + k] = v[k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vector gather of VW consecutive x-points (x0 .. x0+VW-1, nx % VW == 0) of
+// one row, for all 19 directions: q[i][j] = value of direction i at
+// x_j - SIGN*e_i (SIGN = +1: the pull of Algorithm 3; SIGN = -1: the
+// transposed gather x_j + e_i of the adjoint), periodic in x, y and z. When
+// that neighbour is solid the bounced value, direction opp(i) at x_j itself,
+// is taken instead (smask bit b set on point x when x - e_b is solid).
+// Directions with e_x != 0 are single accesses shifted by one element; the
+// row ends are clamped into the row and the wrapped element is loaded on its
+// own, only when the end point needs it (end0/endL: first/last point fluid).
+// Opposite directions (i, i+1), i odd, sit in adjacent planes, so one load
+// with a per-work-item plane choice serves whichever bounced value a
+// work-item needs.
+// ---------------------------------------------------------------------------
+template <int SIGN, int VW, class B>
+__device__ __forceinline__ void gather_vec(const B* __restrict__ src, const Dims& d, uint32_t z,
+                                           uint32_t zm, uint32_t zp, uint32_t orow, uint32_t oym,
+                                           uint32_t oyp, uint32_t x0, bool end0, bool endL,
+                                           bool near_wall, const uint32_t* __restrict__ smask,
+                                           uint32_t c0, typename Vec<B, VW>::t q[Q])
+{
+    using Vt = typename Vec<B, VW>::t;
+    const uint32_t nx = (uint32_t)d.nx;
+    const uint32_t o0 = orow + x0;
+    const bool wl = x0 == 0;
+    const bool wr = x0 + VW == nx;
+    const uint32_t xm = wl ? x0 : x0 - 1;   // group start when reading x - 1
+    const uint32_t xp = wr ? x0 : x0 + 1;   // group start when reading x + 1
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = SIGN * EX[i], ey = SIGN * EY[i];
+        const int iz = SIGN > 0 ? i : OPP[i];   // slab of x - SIGN*e_i
+        uint32_t r = orow;
+        if (ey == 1) r += oym; else if (ey == -1) r += oyp;
+        const uint32_t xs = ex == 1 ? xm : (ex == -1 ? xp : x0);
+        q[i] = ldv<VW>(plane(src, d, i, src_slab(iz, z, zm, zp)), r + xs);
+    }
+    B wrapv[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) wrapv[i] = B(0);
+    const bool fixl = wl && end0, fixr = wr && endL;
+    if (fixl || fixr) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int ex = SIGN * EX[i], ey = SIGN * EY[i];
+            if (ex == 0) continue;
+            const int iz = SIGN > 0 ? i : OPP[i];
+            uint32_t r = orow;
+            if (ey == 1) r += oym; else if (ey == -1) r += oyp;
+            const B* P = plane(src, d, i, src_slab(iz, z, zm, zp));
+            if (ex == 1 && fixl) wrapv[i] = ld(P, r + nx - 1);
+            if (ex == -1 && fixr) wrapv[i] = ld(P, r);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = SIGN * EX[i];
+        if (ex == 0) continue;
+        const Vt v = q[i];
+        Vt s;
+        if (ex == 1) {
+            s[0] = wrapv[i];
+#pragma unroll
+            for (int k = 1; k < VW; ++k) s[k] = v[k - 1];
+            q[i] = wl ? s : v;
+        } else {
+#pragma unroll
+            for (int k = 0; k < VW - 1; ++k) s[k] = v[k + 1];
+            s[VW - 1] = wrapv[i];
+            q[i] = wr ? s : v;
+        }
+    }
+    if (near_wall) {
+        uint32_t sm[VW];
+        load_words<VW>(smask, c0, sm);
+        uint32_t any = 0;
+#pragma unroll
+        for (int j = 0; j < VW; ++j) any |= sm[j];
+        const B* pair_base = plane(src, d, 0, z);
+#pragma unroll
+        for (int i = 1; i < Q; i += 2) {
+            const int k = i + 1;                     // OPP[i] == k
+            const int bi = SIGN > 0 ? i : k;         // mask bit: is q[i]'s neighbour solid
+            const int bk = SIGN > 0 ? k : i;         // mask bit for q[k]
+            const bool need_i = (any >> bi) & 1u, need_k = (any >> bk) & 1u;
+            if (need_i || need_k) {
+                // bounced value of q[i] is direction k at x, of q[k] direction i
+                const uint32_t pl = need_i ? (uint32_t)k : (uint32_t)i;
+                const Vt bb = ldv<VW>(pair_base, pl * d.nxy + o0);
+                const int t = need_i ? bi : bk;
+                Vt v = need_i ? q[i] : q[k];
+#pragma unroll
+                for (int j = 0; j < VW; ++j)
+                    if ((sm[j] >> t) & 1u) v[j] = bb[j];
+                if (need_i) q[i] = v; else q[k] = v;
+                if (need_i && need_k) {
+                    const Vt b2 = ldv<VW>(pair_base, (uint32_t)i * d.nxy + o0);
+                    Vt w = q[k];
+#pragma unroll
+                    for (int j = 0; j < VW; ++j)
+                        if ((sm[j] >> bk) & 1u) w[j] = b2[j];
+                    q[k] = w;
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Collision on offsets. In: h_i = p_i - w_i (pre-collision), force F (zero
 // when FORCE is false). Out: h_i <- s_i - w_i.
@@ -234,9 +355,10 @@ __device__ __forceinline__ float guo(int i, const Macro& m, float Fx, float Fy, 
     return weight(i) * fmaf(9.0f * eu, eF, 3.0f * (eF - uF));
 }
 
+// Returns the in-step macroscopic values (rho, u = (m + F/2)/rho).
 template <bool FORCE>
-__device__ __forceinline__ void bgk_collide(float h[Q], float omega, float cF, float Fx, float Fy,
-                                            float Fz)
+__device__ __forceinline__ Macro bgk_collide(float h[Q], float omega, float cF, float Fx, float Fy,
+                                             float Fz)
 {
     const Macro m = macro_pre<FORCE>(h, Fx, Fy, Fz);
     const float A = eq_A(m);
@@ -248,6 +370,7 @@ __device__ __forceinline__ void bgk_collide(float h[Q], float omega, float cF, f
         if (FORCE) out = fmaf(cF, guo(i, m, Fx, Fy, Fz, uF), out);
         h[i] = out;
     }
+    return m;
 }
 
 }  // namespace d3q19

@@ -27,9 +27,11 @@ Launch make_launch(const d3q19::Dims& d, int bx, int by, hipStream_t s);
 
 // One step. AB: reads `a`, writes `b`. AA: in place on `a`; parity 0 is the
 // gather/scatter step, parity 1 the local step.
+// AB only: rho/u non-null also stores the in-step rho [N] and u [3][N].
 hipError_t launch_step(int storage, int pattern, int parity, bool collide, int force_mode,
                        void* a, void* b, const uint8_t* flags, const float* ffield,
-                       const StepArgs& args, const Launch& L);
+                       const StepArgs& args, const Launch& L, float* rho = nullptr,
+                       float* u = nullptr);
 
 // One AB step with vw consecutive x-points per work-item: vw = 4 (FP32,
 // 16-byte accesses; or 16-bit storage, 8-byte accesses) or vw = 8 (16-bit
@@ -38,7 +40,8 @@ hipError_t launch_step(int storage, int pattern, int parity, bool collide, int f
 bool vector_width_ok(int storage, int vw);
 hipError_t launch_step_abv(int storage, int vw, bool collide, int force_mode, void* a, void* b,
                            const uint8_t* flags, const uint32_t* smask, const uint32_t* mmask,
-                           const float* ffield, const StepArgs& args, const Launch& L);
+                           const float* ffield, const StepArgs& args, const Launch& L,
+                           float* rho = nullptr, float* u = nullptr);
 
 // flags_out = type bits of flags_in plus NEAR_WALL / NEAR_MOVING on fluid
 // cells next to a solid / moving-wall cell; smask / mmask bit i set when
@@ -77,12 +80,19 @@ hipError_t launch_adjoint_seed(int force_mode, const float* f, const uint8_t* fl
                                const float* ffield, const float* g, float* a, float* gF,
                                const StepArgs& args, const Launch& L);
 
-// Reverse step t: a^{t+1} from bin (direct = seed layout, else gathered
+// Reverse step t (at most 256 work-items per group): a^{t+1} from bin (direct = seed layout, else gathered
 // through the transposed streaming), p from the pull gather of state s^t,
 // bout = J_C(p)^T a^{t+1}; grad_F += dC/dF^T a; taupart[block] += dC/dtau . a.
 hipError_t launch_adjoint_step(bool direct, int force_mode, const float* s, const float* bin,
                                float* bout, float* gF, double* taupart, const uint8_t* flags,
                                const float* ffield, const StepArgs& args, float inv_tau2,
                                const Launch& L);
+
+// The same reverse step with vw = 2 or 4 consecutive x-points per work-item
+// (nx % vw == 0, at most 256 work-items per group, grid counting groups).
+hipError_t launch_adjoint_stepv(int vw, bool direct, int force_mode, const float* s, const float* bin,
+                                float* bout, float* gF, double* taupart, const uint8_t* flags,
+                                const uint32_t* smask, const uint32_t* mmask, const float* ffield,
+                                const StepArgs& args, float inv_tau2, const Launch& L);
 
 }  // namespace lbmk

@@ -75,8 +75,95 @@ __global__ __launch_bounds__(1024) void k_adj_seed(const float* __restrict__ f,
     gF[2 * N + c] = gz * h2;
 }
 
+// Transposed collision Jacobian at one point: av = dL/ds (post-collision),
+// h = pre-collision offsets p_i - w_i (moving-wall terms included), force F.
+// Returns b = J_C(p)^T av, the force-gradient increment (gx, gy, gz) and the
+// tau term sum_i av_i [(p_i - f^eq_i) + G_i/2] / tau^2.
+template <bool FORCE>
+__device__ __forceinline__ void adj_cell(const float av[Q], const float h[Q], float Fx, float Fy,
+                                         float Fz, const StepArgs& a, float inv_tau2, float b[Q],
+                                         float& gx, float& gy, float& gz, float& tterm)
+{
+    const Macro m = macro_pre<FORCE>(h, Fx, Fy, Fz);
+    const float A = eq_A(m);
+    const float uF = FORCE ? fmaf(m.ux, Fx, fmaf(m.uy, Fy, m.uz * Fz)) : 0.0f;
+
+    float S = 0.0f, A0 = 0.0f;
+    float A1x = 0.0f, A1y = 0.0f, A1z = 0.0f;   // sum a w e
+    float A2x = 0.0f, A2y = 0.0f, A2z = 0.0f;   // sum a w (e.u) e
+    float A3x = 0.0f, A3y = 0.0f, A3z = 0.0f;   // sum a w (e.F) e
+    float tt = 0.0f, tg = 0.0f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const float he = heq(i, m, A);
+        S = fmaf(av[i], weight(i) + he, S);
+        const float aw = av[i] * weight(i);
+        A0 += aw;
+        const float eu = edot(i, m.ux, m.uy, m.uz);
+        const float awe = aw * eu;
+        if (EX[i]) { A1x += EX[i] * aw; A2x += EX[i] * awe; }
+        if (EY[i]) { A1y += EY[i] * aw; A2y += EY[i] * awe; }
+        if (EZ[i]) { A1z += EZ[i] * aw; A2z += EZ[i] * awe; }
+        tt = fmaf(av[i], h[i] - he, tt);
+        if (FORCE) {
+            const float eF = edot(i, Fx, Fy, Fz);
+            const float awF = aw * eF;
+            if (EX[i]) A3x += EX[i] * awF;
+            if (EY[i]) A3y += EY[i] * awF;
+            if (EZ[i]) A3z += EZ[i] * awF;
+            tg = fmaf(av[i], guo(i, m, Fx, Fy, Fz, uF), tg);
+        }
+    }
+    const float om = a.omega, cF = a.cF;
+    const float ir = 1.0f / m.rho;
+    S *= ir;
+    const float orho = om * m.rho;
+    float Vx = orho * (3.0f * A1x + 9.0f * A2x - 3.0f * m.ux * A0);
+    float Vy = orho * (3.0f * A1y + 9.0f * A2y - 3.0f * m.uy * A0);
+    float Vz = orho * (3.0f * A1z + 9.0f * A2z - 3.0f * m.uz * A0);
+    if (FORCE) {
+        Vx = fmaf(cF, 9.0f * A3x - 3.0f * Fx * A0, Vx);
+        Vy = fmaf(cF, 9.0f * A3y - 3.0f * Fy * A0, Vy);
+        Vz = fmaf(cF, 9.0f * A3z - 3.0f * Fz * A0, Vz);
+    }
+    const float Vu = fmaf(Vx, m.ux, fmaf(Vy, m.uy, Vz * m.uz));
+    const float base = om * S;
+    const float oneMinus = 1.0f - om;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) b[j] = fmaf(oneMinus, av[j], base) + (edot(j, Vx, Vy, Vz) - Vu) * ir;
+    const float Wx = 3.0f * A1x - 3.0f * m.ux * A0 + 9.0f * A2x;
+    const float Wy = 3.0f * A1y - 3.0f * m.uy * A0 + 9.0f * A2y;
+    const float Wz = 3.0f * A1z - 3.0f * m.uz * A0 + 9.0f * A2z;
+    const float h2 = 0.5f * ir;
+    gx = fmaf(Vx, h2, cF * Wx);
+    gy = fmaf(Vy, h2, cF * Wy);
+    gz = fmaf(Vz, h2, cF * Wz);
+    tterm = fmaf(0.5f, tg, tt) * inv_tau2;
+}
+
+// Block sum of per-work-item tau terms in double with a fixed-shape LDS tree
+// (any block size, deterministic); thread 0 adds it to this block's slot.
+__device__ __forceinline__ void block_tau_sum(double v, double* __restrict__ taupart)
+{
+    __shared__ double part[1024];
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int nthreads = blockDim.x * blockDim.y;
+    part[tid] = v;
+    __syncthreads();
+    int span = 1;
+    while (span < nthreads) span <<= 1;
+    for (int sh = span >> 1; sh > 0; sh >>= 1) {
+        if (tid < sh && tid + sh < nthreads) part[tid] += part[tid + sh];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const size_t blk = (size_t)blockIdx.x + (size_t)gridDim.x * ((size_t)blockIdx.y + (size_t)gridDim.y * blockIdx.z);
+        taupart[blk] += part[0];
+    }
+}
+
 template <int FM, bool DIRECT>
-__global__ __launch_bounds__(1024) void k_adj_step(const float* __restrict__ s,
+__global__ __launch_bounds__(256) void k_adj_step(const float* __restrict__ s,
                                                    const float* __restrict__ bin,
                                                    float* __restrict__ bout, float* __restrict__ gF,
                                                    double* __restrict__ taupart,
@@ -130,83 +217,127 @@ __global__ __launch_bounds__(1024) void k_adj_step(const float* __restrict__ s,
         }
         float Fx, Fy, Fz;
         force_at<FM>(a, ff, c, Fx, Fy, Fz);
-        const Macro m = macro_pre<FORCE>(h, Fx, Fy, Fz);
-        const float A = eq_A(m);
-        const float uF = FORCE ? fmaf(m.ux, Fx, fmaf(m.uy, Fy, m.uz * Fz)) : 0.0f;
-
-        float S = 0.0f, A0 = 0.0f;
-        float A1x = 0.0f, A1y = 0.0f, A1z = 0.0f;   // sum a w e
-        float A2x = 0.0f, A2y = 0.0f, A2z = 0.0f;   // sum a w (e.u) e
-        float A3x = 0.0f, A3y = 0.0f, A3z = 0.0f;   // sum a w (e.F) e
-        float tt = 0.0f, tg = 0.0f;
+        float b[Q], gx, gy, gz;
+        adj_cell<FORCE>(av, h, Fx, Fy, Fz, a, inv_tau2, b, gx, gy, gz, tterm);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const float he = heq(i, m, A);
-            S = fmaf(av[i], weight(i) + he, S);
-            const float aw = av[i] * weight(i);
-            A0 += aw;
-            const float eu = edot(i, m.ux, m.uy, m.uz);
-            const float awe = aw * eu;
-            if (EX[i]) { A1x += EX[i] * aw; A2x += EX[i] * awe; }
-            if (EY[i]) { A1y += EY[i] * aw; A2y += EY[i] * awe; }
-            if (EZ[i]) { A1z += EZ[i] * aw; A2z += EZ[i] * awe; }
-            tt = fmaf(av[i], h[i] - he, tt);
-            if (FORCE) {
-                const float eF = edot(i, Fx, Fy, Fz);
-                const float awF = aw * eF;
-                if (EX[i]) A3x += EX[i] * awF;
-                if (EY[i]) A3y += EY[i] * awF;
-                if (EZ[i]) A3z += EZ[i] * awF;
-                tg = fmaf(av[i], guo(i, m, Fx, Fy, Fz, uF), tg);
+        for (int j = 0; j < Q; ++j) st(plane(bout, d, j, z), o, b[j]);
+        gF[c] += gx;
+        gF[N + c] += gy;
+        gF[2 * N + c] += gz;
+    }
+
+    block_tau_sum((double)tterm, taupart);
+}
+
+// Flag bytes of VW consecutive points as one word.
+template <int VW>
+struct FlagBytes;
+template <>
+struct FlagBytes<2> {
+    typedef uint16_t t;
+    static constexpr uint16_t ones = 0x0101u;
+};
+template <>
+struct FlagBytes<4> {
+    typedef uint32_t t;
+    static constexpr uint32_t ones = 0x01010101u;
+};
+
+// Reverse step with VW consecutive x-points per work-item (nx % VW == 0):
+// the state is gathered from x - e_i and the adjoint from x + e_i with the
+// 16-byte shifted accesses of the forward vector kernel (gather_vec); each
+// point then runs the same adj_cell arithmetic as the one-point kernel, so
+// b and dL/dF agree with it bit for bit.
+template <int FM, bool DIRECT, int VW>
+__global__ __launch_bounds__(256) void k_adj_stepv(const float* __restrict__ s,
+                                                   const float* __restrict__ bin,
+                                                   float* __restrict__ bout, float* __restrict__ gF,
+                                                   double* __restrict__ taupart,
+                                                   const uint8_t* __restrict__ flags,
+                                                   const uint32_t* __restrict__ smask,
+                                                   const uint32_t* __restrict__ mmask,
+                                                   const float* __restrict__ ff, StepArgs a,
+                                                   float inv_tau2)
+{
+    using Vt = typename Vec<float, VW>::t;
+    using FW = typename FlagBytes<VW>::t;
+    constexpr bool FORCE = FM != FORCE_NONE;
+    constexpr FW ONES = FlagBytes<VW>::ones;
+    const Dims& d = a.d;
+    const int x0 = VW * (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const uint32_t z = blockIdx.z;
+    const bool inside = x0 < d.nx && y < d.ny;
+    const uint32_t nx = (uint32_t)d.nx;
+    const uint32_t orow = inside ? (uint32_t)y * nx : 0u;
+    const uint32_t o0 = orow + (inside ? (uint32_t)x0 : 0u);
+    const uint32_t c0 = z * d.nxy + o0;
+    const FW flw = inside ? *reinterpret_cast<const FW*>(flags + c0) : ONES;
+    const FW solid = (flw | (flw >> 1)) & ONES;
+    double tsum = 0.0;
+
+    if (solid != ONES) {
+        const size_t N = d.N;
+        const uint32_t zm = wrap_m(z, (uint32_t)d.nz), zp = wrap_p(z, (uint32_t)d.nz);
+        const uint32_t oym = (y == 0) ? (uint32_t)(d.ny - 1) * nx : (uint32_t)0 - nx;
+        const uint32_t oyp = (y == d.ny - 1) ? (uint32_t)(1 - d.ny) * nx : nx;
+        const bool end0 = !(solid & 1u), endL = !((solid >> (8 * (VW - 1))) & 1u);
+        const bool nw = (flw & (ONES * NEAR_WALL)) != 0;
+        Vt hq[Q], aq[Q];
+        gather_vec<+1, VW>(s, d, z, zm, zp, orow, oym, oyp, (uint32_t)x0, end0, endL, nw, smask, c0, hq);
+        if (DIRECT) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) aq[i] = ldv<VW>(plane(bin, d, i, z), o0);
+        } else {
+            gather_vec<-1, VW>(bin, d, z, zm, zp, orow, oym, oyp, (uint32_t)x0, end0, endL, nw, smask, c0, aq);
+        }
+        uint32_t mm[VW];
+#pragma unroll
+        for (int j = 0; j < VW; ++j) mm[j] = 0u;
+        if (flw & (ONES * NEAR_MOVING)) load_words<VW>(mmask, c0, mm);
+        float F[3][VW];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (FM == FORCE_FIELD) {
+                const Vt f = ldv<VW>(ff + k * N, c0);
+#pragma unroll
+                for (int j = 0; j < VW; ++j) F[k][j] = f[j];
+            } else {
+                const float fu = FM == FORCE_UNIFORM ? (k == 0 ? a.Fx : (k == 1 ? a.Fy : a.Fz)) : 0.0f;
+#pragma unroll
+                for (int j = 0; j < VW; ++j) F[k][j] = fu;
             }
         }
-        const float om = a.omega, cF = a.cF;
-        const float ir = 1.0f / m.rho;
-        S *= ir;
-        const float orho = om * m.rho;
-        float Vx = orho * (3.0f * A1x + 9.0f * A2x - 3.0f * m.ux * A0);
-        float Vy = orho * (3.0f * A1y + 9.0f * A2y - 3.0f * m.uy * A0);
-        float Vz = orho * (3.0f * A1z + 9.0f * A2z - 3.0f * m.uz * A0);
-        if (FORCE) {
-            Vx = fmaf(cF, 9.0f * A3x - 3.0f * Fx * A0, Vx);
-            Vy = fmaf(cF, 9.0f * A3y - 3.0f * Fy * A0, Vy);
-            Vz = fmaf(cF, 9.0f * A3z - 3.0f * Fz * A0, Vz);
-        }
-        const float Vu = fmaf(Vx, m.ux, fmaf(Vy, m.uy, Vz * m.uz));
-        const float base = om * S;
-        const float oneMinus = 1.0f - om;
+        Vt gv[3];
 #pragma unroll
-        for (int j = 0; j < Q; ++j) {
-            const float bj = fmaf(oneMinus, av[j], base) + (edot(j, Vx, Vy, Vz) - Vu) * ir;
-            st(plane(bout, d, j, z), o, bj);
+        for (int k = 0; k < 3; ++k) gv[k] = ldv<VW>(gF + k * N, c0);
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+            const bool sol = (solid >> (8 * j)) & 1u;
+            float av[Q], h[Q], b[Q], gx, gy, gz, tt;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                av[i] = aq[i][j];
+                h[i] = hq[i][j] - weight(i);
+                if (i > 0 && ((mm[j] >> i) & 1u)) h[i] = h[i] + a.mw[i];
+            }
+            adj_cell<FORCE>(av, h, F[0][j], F[1][j], F[2][j], a, inv_tau2, b, gx, gy, gz, tt);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) aq[i][j] = sol ? 0.0f : b[i];
+            if (!sol) {
+                gv[0][j] = gv[0][j] + gx;
+                gv[1][j] = gv[1][j] + gy;
+                gv[2][j] = gv[2][j] + gz;
+                tsum += (double)tt;
+            }
         }
-        const float Wx = 3.0f * A1x - 3.0f * m.ux * A0 + 9.0f * A2x;
-        const float Wy = 3.0f * A1y - 3.0f * m.uy * A0 + 9.0f * A2y;
-        const float Wz = 3.0f * A1z - 3.0f * m.uz * A0 + 9.0f * A2z;
-        const float h2 = 0.5f * ir;
-        gF[c] += fmaf(Vx, h2, cF * Wx);
-        gF[N + c] += fmaf(Vy, h2, cF * Wy);
-        gF[2 * N + c] += fmaf(Vz, h2, cF * Wz);
-        tterm = fmaf(0.5f, tg, tt) * inv_tau2;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) stv<VW>(plane(bout, d, i, z), o0, aq[i]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) stv<VW>(gF + k * N, c0, gv[k]);
     }
 
-    // Block sum of the tau terms in double with a fixed-shape LDS tree (any
-    // block size, deterministic); thread 0 adds it to this block's slot.
-    __shared__ double part[1024];
-    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-    const int nthreads = blockDim.x * blockDim.y;
-    part[tid] = (double)tterm;
-    __syncthreads();
-    int span = 1;
-    while (span < nthreads) span <<= 1;
-    for (int sh = span >> 1; sh > 0; sh >>= 1) {
-        if (tid < sh && tid + sh < nthreads) part[tid] += part[tid + sh];
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const size_t blk = (size_t)blockIdx.x + (size_t)gridDim.x * ((size_t)blockIdx.y + (size_t)gridDim.y * blockIdx.z);
-        taupart[blk] += part[0];
-    }
+    block_tau_sum(tsum, taupart);
 }
 
 hipError_t launch_adjoint_seed(int fm, const float* f, const uint8_t* flags, const float* ff,
@@ -236,6 +367,40 @@ static hipError_t adj_fm(bool direct, const float* s, const float* bin, float* b
     else
         hipLaunchKernelGGL((k_adj_step<FM, false>), L.grid, L.block, 0, L.stream, s, bin, bout, gF, tp, flags, ff, a, it2);
     return hipGetLastError();
+}
+
+template <int FM, int VW>
+static hipError_t adjv_fm(bool direct, const float* s, const float* bin, float* bout, float* gF,
+                          double* tp, const uint8_t* flags, const uint32_t* sm, const uint32_t* mm,
+                          const float* ff, const StepArgs& a, float it2, const Launch& L)
+{
+    if (direct)
+        hipLaunchKernelGGL((k_adj_stepv<FM, true, VW>), L.grid, L.block, 0, L.stream, s, bin, bout, gF, tp, flags, sm, mm, ff, a, it2);
+    else
+        hipLaunchKernelGGL((k_adj_stepv<FM, false, VW>), L.grid, L.block, 0, L.stream, s, bin, bout, gF, tp, flags, sm, mm, ff, a, it2);
+    return hipGetLastError();
+}
+
+template <int VW>
+static hipError_t adjv_vw(bool direct, int fm, const float* s, const float* bin, float* bout, float* gF,
+                          double* tp, const uint8_t* flags, const uint32_t* sm, const uint32_t* mm,
+                          const float* ff, const StepArgs& a, float it2, const Launch& L)
+{
+    switch (fm) {
+    case FORCE_UNIFORM: return adjv_fm<FORCE_UNIFORM, VW>(direct, s, bin, bout, gF, tp, flags, sm, mm, ff, a, it2, L);
+    case FORCE_FIELD: return adjv_fm<FORCE_FIELD, VW>(direct, s, bin, bout, gF, tp, flags, sm, mm, ff, a, it2, L);
+    default: return adjv_fm<FORCE_NONE, VW>(direct, s, bin, bout, gF, tp, flags, sm, mm, ff, a, it2, L);
+    }
+}
+
+hipError_t launch_adjoint_stepv(int vw, bool direct, int fm, const float* s, const float* bin, float* bout,
+                                float* gF, double* taupart, const uint8_t* flags, const uint32_t* smask,
+                                const uint32_t* mmask, const float* ff, const StepArgs& args,
+                                float inv_tau2, const Launch& L)
+{
+    if (vw == 2) return adjv_vw<2>(direct, fm, s, bin, bout, gF, taupart, flags, smask, mmask, ff, args, inv_tau2, L);
+    if (vw == 4) return adjv_vw<4>(direct, fm, s, bin, bout, gF, taupart, flags, smask, mmask, ff, args, inv_tau2, L);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_adjoint_step(bool direct, int fm, const float* s, const float* bin, float* bout,

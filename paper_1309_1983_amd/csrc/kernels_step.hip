@@ -40,9 +40,9 @@ __device__ __forceinline__ void load_force(const StepArgs& a, const float* __res
 
 // Decode, add moving-wall terms, collide. h ends as post-collision offsets.
 template <class St, int FM>
-__device__ __forceinline__ void decode_collide(const typename St::raw_t raw[Q], uint32_t mwmask,
-                                               const StepArgs& a, const float* __restrict__ ff,
-                                               uint32_t c, float h[Q])
+__device__ __forceinline__ Macro decode_collide(const typename St::raw_t raw[Q], uint32_t mwmask,
+                                                const StepArgs& a, const float* __restrict__ ff,
+                                                uint32_t c, float h[Q])
 {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -51,7 +51,7 @@ __device__ __forceinline__ void decode_collide(const typename St::raw_t raw[Q], 
     }
     float Fx, Fy, Fz;
     load_force<FM>(a, ff, c, Fx, Fy, Fz);
-    bgk_collide<FM != FORCE_NONE>(h, a.omega, a.cF, Fx, Fy, Fz);
+    return bgk_collide<FM != FORCE_NONE>(h, a.omega, a.cF, Fx, Fy, Fz);
 }
 
 #define POINT_PROLOGUE(d)                                                                      \
@@ -66,19 +66,27 @@ __device__ __forceinline__ void decode_collide(const typename St::raw_t raw[Q], 
 // ---------------------------------------------------------------------------
 // AB pull step, one point per work-item: gather from x - e_i in `src`,
 // bounce back at solid neighbours, collide, store into `dst`. Used when the
-// row length is not a multiple of the vector width.
+// row length is not a multiple of the vector width. MACROS: also store the
+// in-step rho and u (the four extra stores per point of Section 4.1).
 // ---------------------------------------------------------------------------
-template <class St, int FM, bool COLLIDE>
+template <class St, int FM, bool COLLIDE, bool MACROS>
 __global__ __launch_bounds__(1024) void k_step_ab(const typename St::raw_t* __restrict__ src,
                                                   typename St::raw_t* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
-                                                  const float* __restrict__ ff, StepArgs a)
+                                                  const float* __restrict__ ff, StepArgs a,
+                                                  float* __restrict__ rho_out, float* __restrict__ u_out)
 {
     using T = typename St::raw_t;
     const Dims& d = a.d;
     POINT_PROLOGUE(d)
     const uint8_t fl = flags[c];
-    if (fl & TYPE_MASK) return;
+    if (fl & TYPE_MASK) {
+        if (MACROS) {
+            rho_out[c] = 0.0f;
+            u_out[c] = 0.0f; u_out[(size_t)d.N + c] = 0.0f; u_out[2 * (size_t)d.N + c] = 0.0f;
+        }
+        return;
+    }
 
     uint32_t on[Q];
     pull_offsets(d, x, y, on);
@@ -104,21 +112,24 @@ __global__ __launch_bounds__(1024) void k_step_ab(const typename St::raw_t* __re
         return;
     }
     float h[Q];
-    decode_collide<St, FM>(raw, mwmask, a, ff, c, h);
+    const Macro m = decode_collide<St, FM>(raw, mwmask, a, ff, c, h);
 #pragma unroll
     for (int i = 0; i < Q; ++i) st(plane(dst, d, i, z), o, St::enc(h[i], i));
+    if (MACROS) {
+        rho_out[c] = m.rho;
+        u_out[c] = m.ux; u_out[(size_t)d.N + c] = m.uy; u_out[2 * (size_t)d.N + c] = m.uz;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // AB pull step, VW consecutive x-points per work-item (nx % VW == 0), one
 // vector access per direction: 16 bytes for FP32 (VW = 4) and for 16-bit
 // storage with VW = 8, 8 bytes for 16-bit storage with VW = 4.
-// Directions with e_x = 0 are aligned accesses; e_x = +-1 are shifted by one
-// element (a shifted wave access spans one extra cache line, which the
-// neighbouring work-item also touches, so HBM traffic does not grow).
-// Row ends are clamped into the row and the periodic wrap element is loaded
-// on its own, only when the end point is fluid. Near-wall points take the
-// bounced values s_opp(i)(x) through the precomputed solid-neighbour mask.
+// The gather (gather_vec in d3q19.hpp): directions with e_x = 0 are aligned
+// accesses; e_x = +-1 are shifted by one element (a shifted wave access spans
+// one extra cache line, which the neighbouring work-item also touches, so
+// HBM traffic does not grow). Near-wall points take the bounced values
+// s_opp(i)(x) through the precomputed solid-neighbour mask.
 // Solid points inside a work-item's group are written as the rest state.
 // Per fluid point the arithmetic is the one-point kernel's, bit for bit.
 // ---------------------------------------------------------------------------
@@ -135,13 +146,14 @@ struct FlagWord<8> {
     static constexpr uint64_t ones = 0x0101010101010101ull;
 };
 
-template <class St, int FM, bool COLLIDE, int VW>
+template <class St, int FM, bool COLLIDE, int VW, bool MACROS>
 __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __restrict__ src,
                                                   typename St::bits_t* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
                                                   const uint32_t* __restrict__ smask,
                                                   const uint32_t* __restrict__ mmask,
-                                                  const float* __restrict__ ff, StepArgs a)
+                                                  const float* __restrict__ ff, StepArgs a,
+                                                  float* __restrict__ rho_out, float* __restrict__ u_out)
 {
     using B = typename St::bits_t;
     using Vt = typename Vec<B, VW>::t;
@@ -158,91 +170,33 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
     const uint32_t c0 = z * d.nxy + o0;
     const FW flw = *reinterpret_cast<const FW*>(flags + c0);
     const FW solid = (flw | (flw >> 1)) & ONES;   // byte j: point j solid
-    if (solid == ONES) return;
+    if (solid == ONES) {
+        if (MACROS) {
+            const typename Vec<float, VW>::t zero = 0.0f;
+            stv<VW>(rho_out, c0, zero);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) stv<VW>(u_out + k * (size_t)d.N, c0, zero);
+        }
+        return;
+    }
 
     const uint32_t zm = wrap_m(z, (uint32_t)d.nz), zp = wrap_p(z, (uint32_t)d.nz);
     const uint32_t oym = (y == 0) ? (uint32_t)(d.ny - 1) * nx : (uint32_t)0 - nx;
     const uint32_t oyp = (y == d.ny - 1) ? (uint32_t)(1 - d.ny) * nx : nx;
-    const bool wl = x0 == 0;
-    const bool wr = (uint32_t)x0 + VW == nx;
-    const uint32_t xm = wl ? (uint32_t)x0 : (uint32_t)x0 - 1;   // group start for e_x = +1
-    const uint32_t xp = wr ? (uint32_t)x0 : (uint32_t)x0 + 1;   // group start for e_x = -1
 
     Vt q[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        uint32_t r = orow;
-        if (EY[i] == 1) r += oym; else if (EY[i] == -1) r += oyp;
-        const uint32_t xs = EX[i] == 1 ? xm : (EX[i] == -1 ? xp : (uint32_t)x0);
-        q[i] = ldv<VW>(plane(src, d, i, src_slab(i, z, zm, zp)), r + xs);
-    }
+    gather_vec<+1, VW>(src, d, z, zm, zp, orow, oym, oyp, (uint32_t)x0, !(solid & 0x1u),
+                       !((solid >> (8 * (VW - 1))) & 0x1u), (flw & (ONES * NEAR_WALL)) != 0, smask, c0, q);
 
-    // periodic wrap in x at the two row ends
-    const bool fixl = wl && !(solid & 0x1u);
-    const bool fixr = wr && !((solid >> (8 * (VW - 1))) & 0x1u);
-    B wrapv[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) wrapv[i] = B(0);
-    if (fixl || fixr) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            if (EX[i] == 0) continue;
-            uint32_t r = orow;
-            if (EY[i] == 1) r += oym; else if (EY[i] == -1) r += oyp;
-            const B* P = plane(src, d, i, src_slab(i, z, zm, zp));
-            if (EX[i] == 1 && fixl) wrapv[i] = ld(P, r + nx - 1);
-            if (EX[i] == -1 && fixr) wrapv[i] = ld(P, r);
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        if (EX[i] == 0) continue;
-        const Vt v = q[i];
-        Vt s;
-        if (EX[i] == 1) {
-            s[0] = wrapv[i];
-#pragma unroll
-            for (int k = 1; k < VW; ++k) s[k] = v[k - 1];
-            q[i] = wl ? s : v;
-        } else {
-#pragma unroll
-            for (int k = 0; k < VW - 1; ++k) s[k] = v[k + 1];
-            s[VW - 1] = wrapv[i];
-            q[i] = wr ? s : v;
-        }
-    }
-
-    // bounce-back at solid neighbours (points flagged NEAR_WALL)
+    // moving-wall terms of the bounced populations
     uint32_t mm[VW];
 #pragma unroll
     for (int j = 0; j < VW; ++j) mm[j] = 0u;
-    if (flw & (ONES * NEAR_WALL)) {
-        uint32_t sm[VW];
+    if (COLLIDE && (flw & (ONES * NEAR_MOVING))) {
 #pragma unroll
         for (int g = 0; g < VW / 4; ++g) {
-            const typename V4<uint32_t>::t s4 = ld4(smask, c0 + 4 * g);
-            sm[4 * g] = s4.x; sm[4 * g + 1] = s4.y; sm[4 * g + 2] = s4.z; sm[4 * g + 3] = s4.w;
-        }
-        if (COLLIDE && (flw & (ONES * NEAR_MOVING))) {
-#pragma unroll
-            for (int g = 0; g < VW / 4; ++g) {
-                const typename V4<uint32_t>::t m4 = ld4(mmask, c0 + 4 * g);
-                mm[4 * g] = m4.x; mm[4 * g + 1] = m4.y; mm[4 * g + 2] = m4.z; mm[4 * g + 3] = m4.w;
-            }
-        }
-        uint32_t any = 0;
-#pragma unroll
-        for (int j = 0; j < VW; ++j) any |= sm[j];
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            if ((any >> i) & 1u) {
-                const Vt bb = ldv<VW>(plane(src, d, OPP[i], z), o0);
-                Vt v = q[i];
-#pragma unroll
-                for (int j = 0; j < VW; ++j)
-                    if ((sm[j] >> i) & 1u) v[j] = bb[j];
-                q[i] = v;
-            }
+            const typename V4<uint32_t>::t m4 = ld4(mmask, c0 + 4 * g);
+            mm[4 * g] = m4.x; mm[4 * g + 1] = m4.y; mm[4 * g + 2] = m4.z; mm[4 * g + 3] = m4.w;
         }
     }
 
@@ -264,6 +218,7 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
                 F[2][j] = FM == FORCE_UNIFORM ? a.Fz : 0.0f;
             }
         }
+        typename Vec<float, VW>::t mr, mx, my, mz;
 #pragma unroll
         for (int j = 0; j < VW; ++j) {
             float h[Q];
@@ -272,10 +227,22 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
                 h[i] = St::off_b(q[i][j], i);
                 if (i > 0 && ((mm[j] >> i) & 1u)) h[i] = h[i] + a.mw[i];
             }
-            bgk_collide<FM != FORCE_NONE>(h, a.omega, a.cF, F[0][j], F[1][j], F[2][j]);
+            const Macro m = bgk_collide<FM != FORCE_NONE>(h, a.omega, a.cF, F[0][j], F[1][j], F[2][j]);
             const bool sol = (solid >> (8 * j)) & 1u;
 #pragma unroll
             for (int i = 0; i < Q; ++i) q[i][j] = St::enc_b(sol ? 0.0f : h[i], i);
+            if (MACROS) {
+                mr[j] = sol ? 0.0f : m.rho;
+                mx[j] = sol ? 0.0f : m.ux;
+                my[j] = sol ? 0.0f : m.uy;
+                mz[j] = sol ? 0.0f : m.uz;
+            }
+        }
+        if (MACROS) {
+            stv<VW>(rho_out, c0, mr);
+            stv<VW>(u_out, c0, mx);
+            stv<VW>(u_out + (size_t)d.N, c0, my);
+            stv<VW>(u_out + 2 * (size_t)d.N, c0, mz);
         }
     }
 #pragma unroll
@@ -525,16 +492,18 @@ __global__ __launch_bounds__(256) void k_copy(const float* __restrict__ src, flo
 template <class St, int FM>
 static hipError_t step_fm(int pattern, int parity, bool collide, void* a, void* b,
                           const uint8_t* flags, const float* ff, const StepArgs& args,
-                          const Launch& L)
+                          const Launch& L, float* rho, float* u)
 {
     using T = typename St::raw_t;
     T* A = static_cast<T*>(a);
     T* B = static_cast<T*>(b);
     if (pattern == 0) {
-        if (collide)
-            hipLaunchKernelGGL((k_step_ab<St, FM, true>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args);
+        if (collide && rho)
+            hipLaunchKernelGGL((k_step_ab<St, FM, true, true>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
+        else if (collide)
+            hipLaunchKernelGGL((k_step_ab<St, FM, true, false>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
         else
-            hipLaunchKernelGGL((k_step_ab<St, FORCE_NONE, false>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args);
+            hipLaunchKernelGGL((k_step_ab<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
     } else if (parity == 0) {
         if (collide)
             hipLaunchKernelGGL((k_step_aa0<St, FM, true>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
@@ -552,48 +521,52 @@ static hipError_t step_fm(int pattern, int parity, bool collide, void* a, void* 
 template <class St>
 static hipError_t step_st(int pattern, int parity, bool collide, int fm, void* a, void* b,
                           const uint8_t* flags, const float* ff, const StepArgs& args,
-                          const Launch& L)
+                          const Launch& L, float* rho, float* u)
 {
     switch (fm) {
-    case FORCE_UNIFORM: return step_fm<St, FORCE_UNIFORM>(pattern, parity, collide, a, b, flags, ff, args, L);
-    case FORCE_FIELD: return step_fm<St, FORCE_FIELD>(pattern, parity, collide, a, b, flags, ff, args, L);
-    default: return step_fm<St, FORCE_NONE>(pattern, parity, collide, a, b, flags, ff, args, L);
+    case FORCE_UNIFORM: return step_fm<St, FORCE_UNIFORM>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
+    case FORCE_FIELD: return step_fm<St, FORCE_FIELD>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
+    default: return step_fm<St, FORCE_NONE>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
     }
 }
 
 hipError_t launch_step(int storage, int pattern, int parity, bool collide, int force_mode, void* a,
                        void* b, const uint8_t* flags, const float* ffield, const StepArgs& args,
-                       const Launch& L)
+                       const Launch& L, float* rho, float* u)
 {
     switch (storage) {
-    case 1: return step_st<StF16>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L);
-    case 2: return step_st<StBF16>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L);
-    default: return step_st<StF32>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L);
+    case 1: return step_st<StF16>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
+    case 2: return step_st<StBF16>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
+    default: return step_st<StF32>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
     }
 }
 
 template <class St, int FM, int VW>
 static hipError_t stepv_fm(bool collide, void* a, void* b, const uint8_t* flags, const uint32_t* sm,
-                           const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L)
+                           const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L,
+                           float* rho, float* u)
 {
     using B = typename St::bits_t;
     const B* A = static_cast<const B*>(a);
     B* Bp = static_cast<B*>(b);
-    if (collide)
-        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args);
+    if (collide && rho)
+        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, true>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+    else if (collide)
+        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     else
-        hipLaunchKernelGGL((k_step_abv<St, FORCE_NONE, false, VW>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args);
+        hipLaunchKernelGGL((k_step_abv<St, FORCE_NONE, false, VW, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     return hipGetLastError();
 }
 
 template <class St, int VW>
 static hipError_t stepv_st(bool collide, int fm, void* a, void* b, const uint8_t* flags, const uint32_t* sm,
-                           const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L)
+                           const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L,
+                           float* rho, float* u)
 {
     switch (fm) {
-    case FORCE_UNIFORM: return stepv_fm<St, FORCE_UNIFORM, VW>(collide, a, b, flags, sm, mm, ff, args, L);
-    case FORCE_FIELD: return stepv_fm<St, FORCE_FIELD, VW>(collide, a, b, flags, sm, mm, ff, args, L);
-    default: return stepv_fm<St, FORCE_NONE, VW>(collide, a, b, flags, sm, mm, ff, args, L);
+    case FORCE_UNIFORM: return stepv_fm<St, FORCE_UNIFORM, VW>(collide, a, b, flags, sm, mm, ff, args, L, rho, u);
+    case FORCE_FIELD: return stepv_fm<St, FORCE_FIELD, VW>(collide, a, b, flags, sm, mm, ff, args, L, rho, u);
+    default: return stepv_fm<St, FORCE_NONE, VW>(collide, a, b, flags, sm, mm, ff, args, L, rho, u);
     }
 }
 
@@ -601,14 +574,14 @@ bool vector_width_ok(int storage, int vw) { return vw == 4 || (vw == 8 && storag
 
 hipError_t launch_step_abv(int storage, int vw, bool collide, int force_mode, void* a, void* b,
                            const uint8_t* flags, const uint32_t* smask, const uint32_t* mmask,
-                           const float* ffield, const StepArgs& args, const Launch& L)
+                           const float* ffield, const StepArgs& args, const Launch& L, float* rho, float* u)
 {
     switch (storage * 16 + vw) {
-    case 1 * 16 + 8: return stepv_st<StF16, 8>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
-    case 1 * 16 + 4: return stepv_st<StF16, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
-    case 2 * 16 + 8: return stepv_st<StBF16, 8>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
-    case 2 * 16 + 4: return stepv_st<StBF16, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
-    case 0 * 16 + 4: return stepv_st<StF32, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L);
+    case 1 * 16 + 8: return stepv_st<StF16, 8>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
+    case 1 * 16 + 4: return stepv_st<StF16, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
+    case 2 * 16 + 8: return stepv_st<StBF16, 8>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
+    case 2 * 16 + 4: return stepv_st<StBF16, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
+    case 0 * 16 + 4: return stepv_st<StF32, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
     default: return hipErrorInvalidValue;
     }
 }

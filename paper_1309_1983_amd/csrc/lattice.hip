@@ -67,6 +67,7 @@ struct lbm_lattice {
     uint32_t* d_mmask = nullptr;   // moving-wall-neighbour bits per cell
     int* d_check = nullptr;
     int cpl = 1;                   // points per work-item of the AB step (1 or the vector width)
+    bool vec_ok = true;            // vector kernels allowed (cells_per_lane != 1)
     int bx4 = 64, by4 = 1;         // work-group of the vector kernel
 
     bool sticky = false;
@@ -209,7 +210,7 @@ void drop_trajectory(lbm_lattice* L)
 
 void invalidate(lbm_lattice* L) { ++L->version; }
 
-lbm_status run_steps(lbm_lattice* L, int n, bool collide);
+lbm_status run_steps(lbm_lattice* L, int n, bool collide, float* rho = nullptr, float* u = nullptr);
 
 }  // namespace
 
@@ -314,6 +315,7 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
     L->timing_cap = opt.timing_capacity;
     L->check_interval = opt.check_interval;
     L->cpl = cpl;
+    L->vec_ok = opt.cells_per_lane != 1;
     if (cpl > 1) { L->bx4 = bx4; L->by4 = by4; }
 
     lbm_status st = LBM_OK;
@@ -473,6 +475,19 @@ lbm_status lbm_step(lbm_lattice* L, int n)
     return run_steps(L, n, true);
 }
 
+lbm_status lbm_step_macros(lbm_lattice* L, int n, float* rho, float* u)
+{
+    if (!L) return fail(LBM_ERR_INVALID, "lattice is NULL");
+    if (L->sticky) return fail(LBM_ERR_STATE, "lattice is in a failed state after a device error");
+    if (n < 1) return fail(LBM_ERR_INVALID, "n must be >= 1 (got %d)", n);
+    if (!rho || !u) return fail(LBM_ERR_INVALID, "rho and u must both be given");
+    DeviceGuard guard(L->device);
+    if (L->pattern == LBM_PATTERN_AB) return run_steps(L, n, true, rho, u);
+    lbm_status st = run_steps(L, n, true);
+    if (st != LBM_OK) return st;
+    return lbm_macros(L, rho, u);
+}
+
 lbm_status lbm_debug_stream_only(lbm_lattice* L, int n)
 {
     lbm_status st = usable(L);
@@ -627,7 +642,22 @@ lbm_status lbm_adjoint(lbm_lattice* L, const float* g, float* gF, double* grad_t
             if (st != LBM_OK) return st;
         }
     const lbmk::Launch LA = launch_of(L);
-    const size_t nblk = (size_t)LA.grid.x * LA.grid.y * LA.grid.z;
+    // Reverse step: two x-points per work-item with 64-work-item groups (the
+    // fastest shape measured at 256^3; four points need too many registers),
+    // else one point per work-item with at most 256 work-items per group.
+    const bool vec = L->vec_ok && L->nx % 2 == 0;
+    lbmk::Launch LR;
+    if (vec) {
+        d3q19::Dims q = L->dims;
+        q.nx = L->nx / 2;
+        const int rbx = std::min(q.nx, 64);
+        LR = lbmk::make_launch(q, rbx, std::max(1, 64 / rbx), L->stream);
+    } else {
+        int abx, aby;
+        default_block(L->nx, abx, aby);
+        LR = lbmk::make_launch(L->dims, abx, aby, L->stream);
+    }
+    const size_t nblk = (size_t)LR.grid.x * LR.grid.y * LR.grid.z;
     if (L->taupart_n < nblk) {
         dfree(L, L->d_taupart, L->taupart_n * sizeof(double));
         L->d_taupart = nullptr;
@@ -663,8 +693,13 @@ lbm_status lbm_adjoint(lbm_lattice* L, const float* g, float* gF, double* grad_t
                                             L->d_flags, L->d_force, args, LA));
         }
         for (int j = len - 1; j >= 0; --j) {
-            HIPCHK(L, lbmk::launch_adjoint_step(direct, fm, state(j), L->d_adj[ab], L->d_adj[ab ^ 1], gF,
-                                                L->d_taupart, L->d_flags, L->d_force, args, inv_tau2, LA));
+            if (vec)
+                HIPCHK(L, lbmk::launch_adjoint_stepv(2, direct, fm, state(j), L->d_adj[ab], L->d_adj[ab ^ 1], gF,
+                                                     L->d_taupart, L->d_flags, L->d_smask, L->d_mmask, L->d_force,
+                                                     args, inv_tau2, LR));
+            else
+                HIPCHK(L, lbmk::launch_adjoint_step(direct, fm, state(j), L->d_adj[ab], L->d_adj[ab ^ 1], gF,
+                                                    L->d_taupart, L->d_flags, L->d_force, args, inv_tau2, LR));
             ab ^= 1;
             direct = false;
         }
@@ -682,7 +717,9 @@ lbm_status lbm_adjoint(lbm_lattice* L, const float* g, float* gF, double* grad_t
 
 namespace {
 
-lbm_status run_steps(lbm_lattice* L, int n, bool collide)
+// n steps; with rho/u (AB pattern) the last step also stores its in-step
+// rho and u.
+lbm_status run_steps(lbm_lattice* L, int n, bool collide, float* rho, float* u)
 {
     if (n == 0) return LBM_OK;
     const lbmk::StepArgs args = step_args(L);
@@ -695,13 +732,15 @@ lbm_status run_steps(lbm_lattice* L, int n, bool collide)
         L->ev_recorded = 1;
     }
     for (int s = 0; s < n; ++s) {
+        float* mr = s == n - 1 ? rho : nullptr;
+        float* mu = s == n - 1 ? u : nullptr;
         if (L->pattern == LBM_PATTERN_AB && L->cpl > 1) {
             HIPCHK(L, lbmk::launch_step_abv(L->storage, L->cpl, collide, fm, L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags,
-                                            L->d_smask, L->d_mmask, L->d_force, args, LA4));
+                                            L->d_smask, L->d_mmask, L->d_force, args, LA4, mr, mu));
             L->cur ^= 1;
         } else if (L->pattern == LBM_PATTERN_AB) {
             HIPCHK(L, lbmk::launch_step(L->storage, 0, 0, collide, fm, L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags,
-                                        L->d_force, args, LA));
+                                        L->d_force, args, LA, mr, mu));
             L->cur ^= 1;
         } else {
             HIPCHK(L, lbmk::launch_step(L->storage, 1, L->parity, collide, fm, L->d_f[0], nullptr, L->d_flags,

@@ -126,6 +126,13 @@ class Lattice:
     def step(self, n=1):
         _abi.call("lbm_step", self._h, int(n))
 
+    def step_macros(self, n=1):
+        """n steps; the last one also returns its in-step (rho [N], u [3, N])."""
+        rho = torch.empty(self.N, dtype=torch.float32, device=self.device)
+        u = torch.empty(3, self.N, dtype=torch.float32, device=self.device)
+        _abi.call("lbm_step_macros", self._h, int(n), _ptr(rho), _ptr(u))
+        return rho, u
+
     def stream_only(self, n=1):
         _abi.call("lbm_debug_stream_only", self._h, int(n))
 

@@ -151,6 +151,32 @@ def test_f32_step_matches_oracle_after_100_steps(name):
     assert err <= TOL
 
 
+@pytest.mark.parametrize("name,pattern", [("random_walls_field", "ab"), ("random_walls_field_x4", "ab"),
+                                          ("spheres_duct", "ab"), ("random_walls_field_x4", "aa")])
+def test_fused_macros_match_separate_pass_and_oracle(name, pattern):
+    """rho and u written by the step itself (168 B per point variant) equal the
+    separate macroscopic pass over the resulting state to FP32 rounding, and
+    the oracle's macros of its own run, and the populations are unchanged."""
+    shape, tau, flags, uw, force, ff, s0 = _case(name)
+    lat = _lattice(shape, tau, flags=flags, uw=uw, force=force, force_field=ff, pattern=pattern)
+    lat.set_populations(torch.from_numpy(s0))
+    rho_f, u_f = (t.cpu().numpy().astype(np.float64) for t in lat.step_macros(20))
+    rho_s, u_s = (t.cpu().numpy().astype(np.float64) for t in lat.macros())
+    f_fused = lat.populations().cpu().numpy()
+    lat.close()
+    plain = _gpu_run(shape, tau, s0, 20, flags=flags, uw=uw, force=force, force_field=ff, pattern=pattern)
+    fl = flags == 0
+    np.testing.assert_array_equal(f_fused[:, fl], plain[:, fl])
+    assert np.max(np.abs(rho_f - rho_s)[fl]) <= 4e-7
+    assert np.max(np.abs(u_f - u_s)[:, fl]) <= 4e-7
+    assert np.all(rho_f[~fl] == 0) and np.all(u_f[:, ~fl] == 0)
+    olat = oracle_lattice(shape, tau, flags=flags, uw=uw if uw else (0, 0, 0), force=force,
+                          force_field=ff)
+    rho_ref, u_ref = olat.macros(olat.run(s0.astype(np.float64), 20))
+    assert np.max(np.abs(rho_f - rho_ref)[fl]) <= 1e-6
+    assert np.max(np.abs(u_f - u_ref)[:, fl]) <= 1e-6
+
+
 def test_init_equilibrium_matches_oracle():
     shape, tau, flags, uw, force, ff, _ = _case("random_walls_field")
     N = int(np.prod(shape))
