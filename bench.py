@@ -171,6 +171,63 @@ def adjoint_rate(torch, n, T, K, tau):
     return N * T / dt / 1e6, gb
 
 
+def _time_ms(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def access_study(torch, n=256):
+    """Section 4.3 on MI355X: aligned vs misaligned reads and writes over 19
+    vectors of n^3 floats (the pull reads misaligned, the push writes
+    misaligned), offset-by-one row propagation done directly, through LDS
+    or with DPP lane shifts, and the push vs pull iterations."""
+    import workloads as W
+    from paper_1309_1983_amd import study
+    N = n ** 3
+    out = {"vectors": 19, "elements_per_vector": N}
+    src = torch.rand(19, N, device="cuda")
+    dst = torch.empty_like(src)
+    sink = torch.empty(N, device="cuda")
+    rw = {}
+    for width in (1, 4):
+        for mode, roff, woff in (("copy", 0, 0), ("copy", 1, 0), ("copy", 0, 1), ("read", 0, 0),
+                                 ("read", 1, 0), ("write", 0, 0), ("write", 0, 1)):
+            ms = _time_ms(torch, lambda: study.stream(mode, src, dst, sink, N, 19, roff, woff, width), 10)
+            moved = 19 * (N - 1) * 4 * (2 if mode == "copy" else 1) + ((N - 1) * 4 if mode == "read" else 0)
+            key = f"{mode}_r{roff}w{woff}_x{width}"
+            rw[key] = round(moved / (ms * 1e-3) / 1e9, 1)
+            log(f"study {key}: {rw[key]} GB/s")
+    out["read_write_gbs"] = rw
+    rows = 19 * N // n
+    sh = {}
+    a, b = src.view(-1)[: rows * n], dst.view(-1)[: rows * n]
+    for method in ("direct", "direct4", "lds", "dpp"):
+        ms = _time_ms(torch, lambda: study.shift(a, b, n, rows, method), 10)
+        sh[method] = round(2 * rows * n * 4 / (ms * 1e-3) / 1e9, 1)
+        log(f"study shift {method}: {sh[method]} GB/s")
+    out["offset_by_one_gbs"] = sh
+    del src, dst
+    torch.cuda.empty_cache()
+    flags = torch.from_numpy((W.cavity_flags(n, n, n) != 0).astype(np.uint8)).cuda()
+    fa = torch.full((19, N), 1.0 / 36, device="cuda")
+    fb = fa.clone()
+    pp = {}
+    for scheme in ("pull", "push"):
+        ms = _time_ms(torch, lambda: study.step(fa, fb, flags, n, n, n, 0.6, scheme, 256), 20)
+        pp[scheme] = {"mlups": round(N / ms / 1e3, 1), "gbs": round(152 * N / (ms * 1e-3) / 1e9, 1)}
+        log(f"study {scheme} (one point per work-item): {pp[scheme]}")
+    out["one_point_step"] = pp
+    return out
+
+
 def cpu_baseline(n, tau, lid, budget_s=12.0):
     """The FP64 oracle on the host: whole 256^3 cavity steps, as many as fit
     the time budget (at least one)."""
@@ -206,6 +263,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=10000)
+    ap.add_argument("--study", action="store_true",
+                    help="run the memory-access study (Section 4.3 experiments) instead")
     ap.add_argument("--copy-only", action="store_true",
                     help="run only the copy probe (2 GiB float32, 20 launches): counter calibration")
     args = ap.parse_args()
@@ -219,6 +278,10 @@ def main():
     import paper_1309_1983_amd
     paper_1309_1983_amd.lib()
     assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+
+    if args.study:
+        print(json.dumps({"study": access_study(torch, args.n)}), flush=True)
+        return
 
     if args.copy_only:
         cc = copy_ceiling(torch)

@@ -23,6 +23,8 @@ EXPORTS = [
     "lbm_forward_checkpointed", "lbm_adjoint", "lbm_check_finite", "lbm_step_times", "lbm_sync",
     "lbm_device_bytes", "lbm_status_string", "lbm_last_error", "lbm_copy_f32",
 ]
+# include/lbm_study.h
+STUDY_EXPORTS = ["lbm_study_stream", "lbm_study_shift", "lbm_study_step"]
 
 
 class LBMError(RuntimeError):
@@ -92,6 +94,9 @@ def lib():
         "lbm_status_string": (ctypes.c_char_p, [c_int]),
         "lbm_last_error": (ctypes.c_char_p, []),
         "lbm_copy_f32": (c_int, [fp, fp, c_size, vp]),
+        "lbm_study_stream": (c_int, [c_int, fp, fp, fp, c_size, c_int, c_int, c_int, c_int, vp]),
+        "lbm_study_shift": (c_int, [fp, fp, c_int, c_int, c_int, vp]),
+        "lbm_study_step": (c_int, [fp, fp, vp, c_int, c_int, c_int, c_float, c_int, c_int, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

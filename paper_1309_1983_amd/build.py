@@ -14,7 +14,7 @@ LIB = os.path.join(PKG, "liblbm_hip.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels_step.hip", "kernels_adjoint.hip", "lattice.hip"]
+SOURCES = ["kernels_step.hip", "kernels_adjoint.hip", "lattice.hip", "study.hip"]
 
 # -ffp-contract=off: only explicit fmaf contracts, so every kernel that inlines
 # the collision performs the same arithmetic. Packed FP32 instructions are

@@ -11,6 +11,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "lbm.h")
+STUDY_HEADER = os.path.join(ROOT, "include", "lbm_study.h")
 
 
 @pytest.fixture(scope="module")
@@ -23,14 +24,17 @@ def abi():
     return _abi
 
 
-def _declared_functions():
-    text = open(HEADER).read()
+def _declared_functions(header=None):
+    if header is None:
+        return sorted(set(_declared_functions(HEADER)) | set(_declared_functions(STUDY_HEADER)))
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree(abi):
-    assert _declared_functions() == sorted(abi.EXPORTS)
+    assert _declared_functions(HEADER) == sorted(abi.EXPORTS)
+    assert _declared_functions(STUDY_HEADER) == sorted(abi.STUDY_EXPORTS)
 
 
 def test_library_exports_every_declared_symbol(abi):
@@ -112,6 +116,14 @@ def test_calls_on_null_lattice(abi):
     assert L.lbm_adjoint(None, None, None, ctypes.byref(gt)) == abi.LBM_ERR_INVALID
     assert L.lbm_device_bytes(None) == 0
     L.lbm_destroy(None)  # no-op
+
+
+def test_study_calls_reject_bad_arguments(abi):
+    L = abi.lib()
+    assert L.lbm_study_stream(0, None, None, None, 1024, 19, 0, 0, 4, None) == abi.LBM_ERR_INVALID
+    assert L.lbm_study_stream(3, None, None, None, 1024, 19, 0, 0, 4, None) == abi.LBM_ERR_INVALID
+    assert L.lbm_study_shift(None, None, 256, 4, 0, None) == abi.LBM_ERR_INVALID
+    assert L.lbm_study_step(None, None, None, 8, 8, 8, ctypes.c_float(0.8), 0, 64, None) == abi.LBM_ERR_INVALID
 
 
 def test_status_strings(abi):
