@@ -158,7 +158,7 @@ class Lattice:
                             _dp(self.force_field), _dp(self.force), int(bool(collide)), _dp(s),
                             _dp(out))
         if rc != 0:
-            raise ValueError(f"orc_step failed ({rc})")
+            raise ValueError(f"orc_step failed ({rc}: -1 bad flag value, -3 unsolvable on-site node)")
         return out
 
     def run(self, s, nsteps, collide=True):
@@ -167,7 +167,8 @@ class Lattice:
                            _dp(self.force_field), _dp(self.force), int(bool(collide)),
                            int(nsteps), _dp(s))
         if rc != 0:
-            raise ValueError(f"orc_run failed ({rc})")
+            raise ValueError(f"orc_run failed ({rc}: -1 bad flag value, -2 out of memory, "
+                             "-3 unsolvable on-site node)")
         return s
 
     def macros(self, s):
@@ -189,6 +190,8 @@ class Lattice:
         gt = ctypes.c_double(0.0)
         rc = lib().orc_adjoint(self.nx, self.ny, self.nz, self._flags_p, self.tau, _dp(self.uw),
                                _dp(ff), _dp(s0), int(T), _dp(g), _dp(gF), ctypes.byref(gt))
+        if rc == -1:
+            raise ValueError("the oracle adjoint does not cover on-site velocity nodes")
         if rc != 0:
             raise MemoryError("orc_adjoint could not allocate its state history")
         return gF.reshape(3, self.N), gt.value

@@ -20,6 +20,9 @@
  * velocity boundaries and uses no body force):
  *   - walls are halfway bounce-back on flagged solid cells; a moving wall adds
  *     6 w_i rho_w (e_i . u_w) with rho_w = 1 to the bounced population;
+ *   - on-site velocity nodes (the boundary type of the paper's cavity
+ *     validation, Section 5) are lattice nodes on the wall with a prescribed
+ *     velocity; see onsite_node() below;
  *   - the body force follows Guo, Zheng & Shi (2002): u = (m + F/2)/rho and
  *     source (1 - 1/(2 tau)) w_i [3(e_i - u) + 9 (e_i . u) e_i] . F;
  *   - the box is periodic in x, y and z; walls exist only through flags;
@@ -194,7 +197,14 @@ static void force_at(const double* field, const double* uniform, size_t N, size_
     }
 }
 
+/*
+ * Cell types: 0 fluid, 1 wall, 2 wall moving with u_w, 3 on-site velocity
+ * node at rest, 4 on-site velocity node moving with u_w. Types 1 and 2 are
+ * solid; types 0, 3 and 4 are fluid nodes that stream and collide.
+ */
 static int flag_at(const uint8_t* flags, size_t c) { return flags ? flags[c] : 0; }
+static int is_solid(int fl) { return fl == 1 || fl == 2; }
+static int is_onsite(int fl) { return fl == 3 || fl == 4; }
 
 /*
  * Pull gather for fluid cell (x,y,z): p_i = s_i(x - e_i), or, when x - e_i is
@@ -210,7 +220,7 @@ static void pull(int nx, int ny, int nz, const uint8_t* flags, const double* uw,
         int xs = wrap(x - E[i][0], nx), ys = wrap(y - E[i][1], ny), zs = wrap(z - E[i][2], nz);
         size_t src = cell_index(xs, ys, zs, nx, ny);
         int fl = flag_at(flags, src);
-        if (fl == 0) {
+        if (!is_solid(fl)) {
             p[i] = s[(size_t)i * N + src];
         } else {
             p[i] = s[(size_t)opposite(i) * N + c];
@@ -222,26 +232,129 @@ static void pull(int nx, int ny, int nz, const uint8_t* flags, const double* uw,
     }
 }
 
+/* Solve the 4x4 system A z = r by Gaussian elimination with partial
+ * pivoting. Returns -1 when a pivot vanishes. */
+static int solve4(double A[4][4], double r[4], double z[4])
+{
+    for (int k = 0; k < 4; ++k) {
+        int piv = k;
+        for (int i = k + 1; i < 4; ++i)
+            if (fabs(A[i][k]) > fabs(A[piv][k])) piv = i;
+        if (fabs(A[piv][k]) < 1e-300) return -1;
+        if (piv != k) {
+            for (int j = 0; j < 4; ++j) {
+                double t = A[k][j]; A[k][j] = A[piv][j]; A[piv][j] = t;
+            }
+            double t = r[k]; r[k] = r[piv]; r[piv] = t;
+        }
+        for (int i = k + 1; i < 4; ++i) {
+            double f = A[i][k] / A[k][k];
+            for (int j = k; j < 4; ++j) A[i][j] -= f * A[k][j];
+            r[i] -= f * r[k];
+        }
+    }
+    for (int k = 3; k >= 0; --k) {
+        double v = r[k];
+        for (int j = k + 1; j < 4; ++j) v -= A[k][j] * z[j];
+        z[k] = v / A[k][k];
+    }
+    return 0;
+}
+
+/*
+ * On-site velocity node (the boundary condition family the paper validates
+ * with, Section 5, after Hecht & Harting). The node sits on the wall and its
+ * velocity u is prescribed. After the pull, the populations that would have
+ * come from solid cells (unknown[i] != 0) are missing and are rebuilt here.
+ * The paper prints no formulas; the reading adopted:
+ *   - an unknown direction i whose opposite is known takes the opposite's
+ *     value plus the equilibrium difference and a transverse correction:
+ *       p_i = p_opp(i) + 6 w_i e_i . j + e_i . lambda,   j = rho u - F/2
+ *     (j is the bare momentum that gives velocity u once the Guo term F/2 is
+ *     added in the collision);
+ *   - when both i and opp(i) are unknown (edges and corners of a box), the
+ *     pair takes the equilibrium at (rho, u), split so that it carries the
+ *     same bare momentum: p_i = f^eq_i(rho, u) - (3/2) w_i e_i . F;
+ *   - rho and lambda are whatever makes the node carry mass rho and bare
+ *     momentum j: sum_i p_i = rho and sum_i e_i p_i = j.
+ * The populations are affine in z = (rho, lambda_x, lambda_y, lambda_z), so
+ * the four conditions form a 4x4 linear system, solved directly.
+ * Returns -1 if the system is singular.
+ */
+static int onsite_node(double* p, const int* unknown, const double* u, const double* F)
+{
+    double base[Q], coef[Q][4];
+    for (int i = 0; i < Q; ++i) {
+        for (int k = 0; k < 4; ++k) coef[i][k] = 0.0;
+        base[i] = p[i];
+        if (!unknown[i]) continue;
+        double eu = E[i][0] * u[0] + E[i][1] * u[1] + E[i][2] * u[2];
+        double eF = E[i][0] * F[0] + E[i][1] * F[1] + E[i][2] * F[2];
+        int o = opposite(i);
+        if (!unknown[o]) {
+            /* p_opp + 6 w_i e_i.(rho u - F/2) + e_i.lambda */
+            base[i] = p[o] - 3.0 * weight(i) * eF;
+            coef[i][0] = 6.0 * weight(i) * eu;
+            for (int a = 0; a < 3; ++a) coef[i][1 + a] = E[i][a];
+        } else {
+            /* rho w_i (1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u.u) - 1.5 w_i e_i.F */
+            double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            base[i] = -1.5 * weight(i) * eF;
+            coef[i][0] = weight(i) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * usq);
+        }
+    }
+    /* row 0: sum p - rho = 0; row 1+a: sum e_a p - (rho u_a - F_a/2) = 0 */
+    double A[4][4], r[4], z[4];
+    for (int row = 0; row < 4; ++row) {
+        double rb = 0.0;
+        for (int k = 0; k < 4; ++k) A[row][k] = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            double m = row == 0 ? 1.0 : (double)E[i][row - 1];
+            rb += m * base[i];
+            for (int k = 0; k < 4; ++k) A[row][k] += m * coef[i][k];
+        }
+        if (row == 0) {
+            A[0][0] -= 1.0;
+            r[0] = -rb;
+        } else {
+            A[row][0] -= u[row - 1];
+            r[row] = -(rb + 0.5 * F[row - 1]);
+        }
+    }
+    if (solve4(A, r, z) != 0) return -1;
+    for (int i = 0; i < Q; ++i) {
+        if (!unknown[i]) continue;
+        double v = base[i];
+        for (int k = 0; k < 4; ++k) v += coef[i][k] * z[k];
+        p[i] = v;
+    }
+    return 0;
+}
+
 /*
  * One fused pull iteration (Algorithm 3) over the whole box.
- * collide = 0 gives streaming with bounce-back only (no moving-wall term):
- * an exact permutation of the fluid populations.
- * Solid cells are copied unchanged. Returns 0, or -1 on a bad flag value.
+ * collide = 0 gives streaming with bounce-back only (no moving-wall term, and
+ * on-site nodes treated as ordinary fluid nodes): an exact permutation of the
+ * fluid populations.
+ * Solid cells are copied unchanged. Returns 0, -1 on a bad flag value, -3
+ * when an on-site node's conditions cannot be solved.
  */
 int orc_step(int nx, int ny, int nz, const uint8_t* flags, double tau, const double* uw,
              const double* force_field, const double* force_uniform, int collide,
              const double* s_in, double* s_out)
 {
     size_t N = (size_t)nx * ny * nz;
+    int bad = 0;
     if (flags)
         for (size_t c = 0; c < N; ++c)
-            if (flags[c] > 2) return -1;
-#pragma omp parallel for schedule(static)
+            if (flags[c] > 4) return -1;
+#pragma omp parallel for schedule(static) reduction(| : bad)
     for (int z = 0; z < nz; ++z) {
         for (int y = 0; y < ny; ++y) {
             for (int x = 0; x < nx; ++x) {
                 size_t c = cell_index(x, y, z, nx, ny);
-                if (flag_at(flags, c) != 0) {
+                int fl = flag_at(flags, c);
+                if (is_solid(fl)) {
                     for (int i = 0; i < Q; ++i) s_out[(size_t)i * N + c] = s_in[(size_t)i * N + c];
                     continue;
                 }
@@ -249,6 +362,18 @@ int orc_step(int nx, int ny, int nz, const uint8_t* flags, double tau, const dou
                 pull(nx, ny, nz, flags, uw, collide, s_in, x, y, z, p);
                 if (collide) {
                     force_at(force_field, force_uniform, N, c, F);
+                    if (is_onsite(fl)) {
+                        int unknown[Q];
+                        double un[3] = {0.0, 0.0, 0.0};
+                        for (int i = 0; i < Q; ++i) {
+                            size_t src = cell_index(wrap(x - E[i][0], nx), wrap(y - E[i][1], ny),
+                                                    wrap(z - E[i][2], nz), nx, ny);
+                            unknown[i] = is_solid(flag_at(flags, src));
+                        }
+                        if (fl == 4 && uw)
+                            for (int a = 0; a < 3; ++a) un[a] = uw[a];
+                        if (onsite_node(p, unknown, un, F) != 0) bad = 1;
+                    }
                     orc_collide_cell(p, F, tau, s);
                 } else {
                     for (int i = 0; i < Q; ++i) s[i] = p[i];
@@ -257,7 +382,7 @@ int orc_step(int nx, int ny, int nz, const uint8_t* flags, double tau, const dou
             }
         }
     }
-    return 0;
+    return bad ? -3 : 0;
 }
 
 /* n steps in place on s (uses one scratch copy). Returns 0, -1 bad flags, -2 OOM. */
@@ -288,7 +413,7 @@ void orc_macros(int nx, int ny, int nz, const uint8_t* flags, const double* forc
 {
     size_t N = (size_t)nx * ny * nz;
     for (size_t c = 0; c < N; ++c) {
-        if (flag_at(flags, c) != 0) {
+        if (is_solid(flag_at(flags, c))) {
             rho[c] = 0.0;
             u[c] = u[N + c] = u[2 * N + c] = 0.0;
             continue;
@@ -374,7 +499,9 @@ void orc_quantize(size_t N, int format, const double* f, double* out)
  * g = dL/du(T) as [3][N] (zero at solid cells). All T+1 states are kept.
  * For each step, the 19x19 collision Jacobian of every fluid cell is formed
  * explicitly and multiplied plainly; streaming is transposed link by link.
- * grad_F: [3][N] out; *grad_tau out. Returns 0, or -2 on allocation failure.
+ * grad_F: [3][N] out; *grad_tau out. Returns 0, -1 when the lattice has
+ * on-site velocity nodes (not covered by this adjoint), or -2 on allocation
+ * failure.
  */
 int orc_adjoint(int nx, int ny, int nz, const uint8_t* flags, double tau, const double* uw,
                 const double* force_field, const double* s0, int T, const double* g,
@@ -382,6 +509,9 @@ int orc_adjoint(int nx, int ny, int nz, const uint8_t* flags, double tau, const 
 {
     size_t N = (size_t)nx * ny * nz;
     size_t SZ = (size_t)Q * N;
+    if (flags)
+        for (size_t c = 0; c < N; ++c)
+            if (flags[c] > 2) return -1;
     double* states = (double*)malloc(sizeof(double) * SZ * (size_t)(T + 1));
     double* a = (double*)malloc(sizeof(double) * SZ);
     double* b = (double*)malloc(sizeof(double) * SZ);

@@ -5,7 +5,10 @@ fields and random population arrays. It contains none of the lattice
 Boltzmann arithmetic: no velocity set, no weights, no equilibrium. Both the
 HIP path and the oracle receive exactly these arrays.
 
-Flag values: 0 = fluid, 1 = resting wall, 2 = moving wall. Arrays are flat in
+Flag values: 0 = fluid, 1 = resting wall, 2 = moving wall, 3 = on-site
+velocity node at rest, 4 = on-site velocity node moving with the wall
+velocity (walls 1 and 2 are solid cells; on-site nodes are fluid nodes that
+lie on the wall). Arrays are flat in
 the order x fastest, then y, then z (idx = (z*ny + y)*nx + x); vector fields
 are [3][N] (component slowest).
 """
@@ -13,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-FLUID, WALL, MOVING_WALL = 0, 1, 2
+FLUID, WALL, MOVING_WALL, ONSITE, ONSITE_MOVING = 0, 1, 2, 3, 4
 
 
 def _grid(nx, ny, nz):
@@ -52,6 +55,39 @@ def channel_flags(n_fluid, nx=1, nz=1, lid=False):
     f = np.zeros((nz, ny, nx), dtype=np.uint8)
     f[:, 0, :] = WALL
     f[:, -1, :] = MOVING_WALL if lid else WALL
+    return f.reshape(-1)
+
+
+def onsite_cavity_flags(nx, ny, nz):
+    """Lid-driven cavity with on-site velocity nodes: a one-cell solid frame on
+    every face of the box, and the next layer inward made of on-site nodes.
+    The on-site nodes of the y = ny-2 plane (its edges and corners included)
+    move with the lid; all other on-site nodes are at rest. The walls lie on
+    the node planes x = 1, nx-2 (and likewise in y, z), so the cavity side is
+    nx - 3 lattice spacings."""
+    f = np.zeros((nz, ny, nx), dtype=np.uint8)
+    f[1:-1, 1:-1, 1:-1] = ONSITE
+    f[2:-2, 2:-2, 2:-2] = FLUID
+    f[1:-1, -2, 1:-1] = ONSITE_MOVING
+    f[0, :, :] = WALL
+    f[-1, :, :] = WALL
+    f[:, 0, :] = WALL
+    f[:, -1, :] = WALL
+    f[:, :, 0] = WALL
+    f[:, :, -1] = WALL
+    return f.reshape(-1)
+
+
+def onsite_channel_flags(h, nx=1, nz=1, lid=False):
+    """Plane channel whose walls are on-site nodes at y = 1 and y = h + 1
+    (wall distance h), with solid cells at y = 0 and y = h + 2, periodic in x
+    and z. lid=True makes the top nodes move with the wall velocity."""
+    ny = h + 3
+    f = np.zeros((nz, ny, nx), dtype=np.uint8)
+    f[:, 0, :] = WALL
+    f[:, 1, :] = ONSITE
+    f[:, -2, :] = ONSITE_MOVING if lid else ONSITE
+    f[:, -1, :] = WALL
     return f.reshape(-1)
 
 
