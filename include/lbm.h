@@ -15,10 +15,23 @@
  *     [19][N] array (structure of arrays, Section 4.1).
  *   - Velocity set: the 19 vectors of Eq. (4), in that order.
  *   - Flags (one byte per point): 0 = fluid, 1 = resting wall, 2 = moving
- *     wall. Walls are halfway bounce-back: a fluid point whose neighbour
- *     x - e_i is solid takes the population it sent towards that wall,
- *     s_opp(i)(x), plus 6 w_i (e_i . u_wall) for a moving wall (wall density
- *     1). The box is periodic in x, y and z; walls come only from flags.
+ *     wall, 3 = on-site velocity node at rest, 4 = on-site velocity node
+ *     moving with u_wall. Values 1 and 2 are solid. Walls are halfway
+ *     bounce-back: a fluid point whose neighbour x - e_i is solid takes the
+ *     population it sent towards that wall, s_opp(i)(x), plus
+ *     6 w_i (e_i . u_wall) for a moving wall (wall density 1). The box is
+ *     periodic in x, y and z; walls come only from flags.
+ *   - On-site velocity nodes (values 3, 4; the boundary type of the paper's
+ *     cavity validation, Section 5) are fluid points on a box face, edge or
+ *     corner whose solid neighbours are exactly the cells beyond one to three
+ *     axis-aligned walls. After the gather, the populations that would come
+ *     from solid cells are rebuilt so that the node carries its prescribed
+ *     velocity and a density fixed by mass balance: an unknown population
+ *     whose opposite is known takes that opposite plus 6 w_i e_i . j plus a
+ *     transverse correction (j = rho u - F/2), and a pair of opposite
+ *     unknowns (edges, corners) takes the equilibrium at (rho, u). The
+ *     prescribed velocity is u_wall for value 4 and zero for value 3; the
+ *     macroscopic output reports it exactly (up to rounding).
  *   - Body force (optional): Guo forcing, u = (m + F/2)/rho and source
  *     (1 - 1/(2 tau)) w_i [3(e_i - u) + 9 (e_i . u) e_i] . F.
  *   - The state is the array of post-collision populations. Values stored
@@ -102,8 +115,10 @@ void lbm_options_default(lbm_options* opt);
  * at rest (rho = 1, u = 0: f_i = w_i). flags_host: N bytes in index order,
  * or NULL for all fluid; copied, so the caller may free it on return.
  * Errors: LBM_ERR_INVALID if any n <= 0, N >= 2^30, tau <= 0.5 or not
- * finite, a flag value > 2, or out == NULL; LBM_ERR_OOM; LBM_ERR_DEVICE.
- * All argument checks happen before any HIP call.
+ * finite, a flag value > 4, or out == NULL (checked before any HIP call),
+ * and for an on-site node whose solid neighbours do not form a box face,
+ * edge or corner (found on the device during creation); LBM_ERR_OOM;
+ * LBM_ERR_DEVICE.
  */
 lbm_status lbm_create(int nx, int ny, int nz, float tau, const uint8_t* flags_host,
                       lbm_lattice** out);
@@ -128,8 +143,9 @@ lbm_status lbm_set_stream(lbm_lattice* lat, void* hip_stream);
 /* Relaxation time (Eq. (2)); tau > 0.5. Invalidates a recorded trajectory. */
 lbm_status lbm_set_tau(lbm_lattice* lat, float tau);
 
-/* Velocity of all flag-2 points (Section 5 uses a moving lid). Each
- * component must be finite and |u| < 0.3 (low-Mach guard). */
+/* Velocity of all flag-2 points and of the flag-4 on-site nodes (Section 5
+ * uses a moving lid). Each component must be finite and |u| < 0.3
+ * (low-Mach guard). */
 lbm_status lbm_set_wall_velocity(lbm_lattice* lat, float ux, float uy, float uz);
 
 /* Uniform body force (Guo forcing); clears a force field. Invalidates a
@@ -174,14 +190,16 @@ lbm_status lbm_get_populations(lbm_lattice* lat, float* f_dev);
 lbm_status lbm_set_populations(lbm_lattice* lat, const float* f_dev);
 
 /* Test hook: n steps of pull streaming with bounce-back and no collision
- * and no moving-wall term (an exact permutation of the stored values). */
+ * and no moving-wall term (an exact permutation of the stored values);
+ * on-site nodes stream like plain fluid points here. */
 lbm_status lbm_debug_stream_only(lbm_lattice* lat, int n);
 
 /*
  * Runs T steps from the current state and keeps the states at steps 0, K,
  * 2K, ... in device memory for lbm_adjoint (checkpoint-every-K). A last
- * segment shorter than K is allowed. F32 storage and the AB pattern only.
- * Errors: LBM_ERR_INVALID (T < 0, K <= 0); LBM_ERR_STATE (other storage or
+ * segment shorter than K is allowed. F32 storage, the AB pattern and
+ * lattices without on-site nodes only.
+ * Errors: LBM_ERR_INVALID (T < 0, K <= 0); LBM_ERR_STATE (on-site nodes, other storage or
  * pattern); LBM_ERR_OOM.
  */
 lbm_status lbm_forward_checkpointed(lbm_lattice* lat, int T, int K);

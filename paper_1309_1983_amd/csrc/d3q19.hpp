@@ -36,6 +36,10 @@ constexpr uint8_t MOVING = 2;
 constexpr uint8_t NEAR_WALL = 4;
 // bit 3 set on fluid cells with at least one moving-wall neighbour.
 constexpr uint8_t NEAR_MOVING = 8;
+// bit 4: on-site velocity node, a fluid node lying on the wall whose velocity
+// is prescribed (type bits 0); bit 5: that velocity is u_w, else zero.
+constexpr uint8_t ONSITE_NODE = 16;
+constexpr uint8_t ONSITE_MOVING = 32;
 
 // ---------------------------------------------------------------------------
 // Storage codecs. raw_t is what lives in HBM; off() decodes the offset
@@ -53,13 +57,24 @@ struct StF32 {
     static __device__ __forceinline__ raw_t from_plain(float f, int) { return f; }
 };
 
+// The FP32 result itself is what gets rounded to a 16-bit format. Without
+// this barrier the compiler may merge the last fma of the collision and the
+// conversion into one mixed-precision fma (v_fma_mixlo_f16), which rounds the
+// exact product-sum once instead of the FP32 value; it does so in some kernels
+// and not in others, which would make kernels disagree in the last bit.
+__device__ __forceinline__ float fp32_value(float v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
 struct StF16 {
     using raw_t = _Float16;
     using bits_t = uint16_t;
     static __device__ __forceinline__ float off_b(bits_t b, int) { return (float)__builtin_bit_cast(_Float16, b); }
-    static __device__ __forceinline__ bits_t enc_b(float h, int) { return __builtin_bit_cast(uint16_t, (_Float16)h); }
+    static __device__ __forceinline__ bits_t enc_b(float h, int) { return __builtin_bit_cast(uint16_t, (_Float16)fp32_value(h)); }
     static __device__ __forceinline__ float off(raw_t r, int) { return (float)r; }
-    static __device__ __forceinline__ raw_t enc(float h, int) { return (_Float16)h; }
+    static __device__ __forceinline__ raw_t enc(float h, int) { return (_Float16)fp32_value(h); }
     static __device__ __forceinline__ float plain(raw_t r, int i) { return weight(i) + (float)r; }
     static __device__ __forceinline__ raw_t from_plain(float f, int i) { return (_Float16)(f - weight(i)); }
 };
@@ -68,9 +83,9 @@ struct StBF16 {
     using raw_t = __bf16;
     using bits_t = uint16_t;
     static __device__ __forceinline__ float off_b(bits_t b, int) { return __uint_as_float((uint32_t)b << 16); }
-    static __device__ __forceinline__ bits_t enc_b(float h, int) { return __builtin_bit_cast(uint16_t, (__bf16)h); }
+    static __device__ __forceinline__ bits_t enc_b(float h, int) { return __builtin_bit_cast(uint16_t, (__bf16)fp32_value(h)); }
     static __device__ __forceinline__ float off(raw_t r, int) { return (float)r; }
-    static __device__ __forceinline__ raw_t enc(float h, int) { return (__bf16)h; }
+    static __device__ __forceinline__ raw_t enc(float h, int) { return (__bf16)fp32_value(h); }
     static __device__ __forceinline__ float plain(raw_t r, int i) { return weight(i) + (float)r; }
     static __device__ __forceinline__ raw_t from_plain(float f, int i) { return (__bf16)(f - weight(i)); }
 };
@@ -353,6 +368,118 @@ __device__ __forceinline__ float guo(int i, const Macro& m, float Fx, float Fy, 
     const float eu = edot(i, m.ux, m.uy, m.uz);
     const float eF = edot(i, Fx, Fy, Fz);
     return weight(i) * fmaf(9.0f * eu, eF, 3.0f * (eF - uF));
+}
+
+// ---------------------------------------------------------------------------
+// On-site velocity nodes (the boundary family of the paper's cavity
+// validation, Section 5, after Hecht & Harting). A node on a box face, edge or
+// corner has a prescribed velocity u; the directions whose pull source is
+// solid (bits of U) are unknown after the gather and are rebuilt before the
+// collision so that the node carries mass rho and bare momentum
+// j = rho u - F/2 (velocity u once the collision adds F/2):
+//   - unknown i with known opposite:  f_i = f_opp(i) + 6 w_i e_i.j + e_i.lambda
+//   - both i and opp(i) unknown (edge and corner nodes): the pair takes the
+//     equilibrium at (rho, u) and carries j: f_i = f^eq_i(rho, u) - 1.5 w_i e_i.F
+//   - mass:  rho (1 - W_B - a.u - B_q) = 1 - W_B + H - a.F/2, in offsets
+//       delta = rho - 1 = (H + a.u + B_q - a.F/2) / (1 - W_B - a.u - B_q)
+//     with H = sum of the known offsets and of the opposites of the bounced
+//     ones, a = 6 sum w_i e_i over the bounced unknowns, W_B and
+//     B_q = sum w_i (4.5 (e_i.u)^2 - 1.5 u.u) over the buried pairs;
+//   - the momentum along the axes normal to the wall then holds by itself;
+//     along each tangential axis t the remainder R_t is spread over the
+//     bounced unknowns with e_it != 0: lambda_t = R_t / #{such links}.
+// Mass and momentum hold exactly (up to rounding) on faces, edges and
+// corners; on faces this is the Zou-He / Hecht-Harting rule.
+// ---------------------------------------------------------------------------
+
+// Bits of the directions opposite to those set in m (pairs (1,2) .. (17,18)).
+__device__ __forceinline__ uint32_t opp_bits(uint32_t m)
+{
+    return ((m & 0x2AAAAu) << 1) | ((m & 0x55554u) >> 1);
+}
+
+// Direction bits with a non-zero x, y or z component.
+constexpr uint32_t axis_bits(int axis)
+{
+    uint32_t b = 0;
+    for (int i = 0; i < Q; ++i)
+        if ((axis == 0 ? EX[i] : (axis == 1 ? EY[i] : EZ[i])) != 0) b |= 1u << i;
+    return b;
+}
+
+// U is a valid unknown set: the union over one to three axis-aligned walls of
+// the directions pointing away from that wall (box face, edge or corner).
+__device__ __forceinline__ bool onsite_pattern_ok(uint32_t U)
+{
+    const bool xm = (U >> 1) & 1u, xp = (U >> 2) & 1u;
+    const bool ym = (U >> 3) & 1u, yp = (U >> 4) & 1u;
+    const bool zm = (U >> 5) & 1u, zp = (U >> 6) & 1u;
+    if ((xm && xp) || (ym && yp) || (zm && zp)) return false;
+    uint32_t expect = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const bool in = (xm && EX[i] == 1) || (xp && EX[i] == -1) || (ym && EY[i] == 1) ||
+                        (yp && EY[i] == -1) || (zm && EZ[i] == 1) || (zp && EZ[i] == -1);
+        if (in) expect |= 1u << i;
+    }
+    return U != 0 && U == expect;
+}
+
+// h: offsets after the gather (entries in U arbitrary) -> rebuilt offsets.
+template <bool FORCE>
+__device__ __forceinline__ void onsite_rebuild(float h[Q], uint32_t U, float ux, float uy, float uz,
+                                               float Fx, float Fy, float Fz)
+{
+    const uint32_t Bm = U & opp_bits(U);   // buried pairs
+    const uint32_t Rm = U & ~Bm;           // bounced unknowns
+    const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
+    float H = 0.0f, ax = 0.0f, ay = 0.0f, az = 0.0f, WB = 0.0f, Bq = 0.0f;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const bool rb = (Rm >> i) & 1u, bu = (Bm >> i) & 1u;
+        H += bu ? 0.0f : (rb ? h[OPP[i]] : h[i]);
+        const float w6 = 6.0f * weight(i);
+        ax += rb ? w6 * (float)EX[i] : 0.0f;
+        ay += rb ? w6 * (float)EY[i] : 0.0f;
+        az += rb ? w6 * (float)EZ[i] : 0.0f;
+        const float eu = edot(i, ux, uy, uz);
+        WB += bu ? weight(i) : 0.0f;
+        Bq += bu ? weight(i) * fmaf(4.5f * eu, eu, -1.5f * usq) : 0.0f;
+    }
+    const float au = fmaf(ax, ux, fmaf(ay, uy, az * uz));
+    float num = H + au + Bq;
+    if (FORCE) num = fmaf(-0.5f, fmaf(ax, Fx, fmaf(ay, Fy, az * Fz)), num);
+    const float delta = num / (((1.0f - WB) - au) - Bq);
+    const float rho = 1.0f + delta;
+    float jx = rho * ux, jy = rho * uy, jz = rho * uz;
+    if (FORCE) {
+        jx = fmaf(-0.5f, Fx, jx);
+        jy = fmaf(-0.5f, Fy, jy);
+        jz = fmaf(-0.5f, Fz, jz);
+    }
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const float w = weight(i);
+        if ((Rm >> i) & 1u) {
+            h[i] = fmaf(6.0f * w, edot(i, jx, jy, jz), h[OPP[i]]);
+        } else if ((Bm >> i) & 1u) {
+            const float eu = edot(i, ux, uy, uz);
+            float v = w * fmaf(rho, fmaf(eu, fmaf(4.5f, eu, 3.0f), -1.5f * usq), delta);
+            if (FORCE) v = fmaf(-1.5f * w, edot(i, Fx, Fy, Fz), v);
+            h[i] = v;
+        }
+    }
+    // tangential momentum remainder
+    const bool tx = (U & 0x6u) == 0, ty = (U & 0x18u) == 0, tz = (U & 0x60u) == 0;
+    const int nx = __builtin_popcount(Rm & axis_bits(0));
+    const int ny = __builtin_popcount(Rm & axis_bits(1));
+    const int nz = __builtin_popcount(Rm & axis_bits(2));
+    const float lx = (tx && nx > 0) ? (jx - mom_x(h)) / (float)nx : 0.0f;
+    const float ly = (ty && ny > 0) ? (jy - mom_y(h)) / (float)ny : 0.0f;
+    const float lz = (tz && nz > 0) ? (jz - mom_z(h)) / (float)nz : 0.0f;
+#pragma unroll
+    for (int i = 1; i < Q; ++i)
+        if ((Rm >> i) & 1u) h[i] += edot(i, lx, ly, lz);
 }
 
 // Returns the in-step macroscopic values (rho, u = (m + F/2)/rho).

@@ -16,6 +16,7 @@ struct StepArgs {
     float cF;      // 1 - 1/(2 tau)
     float Fx, Fy, Fz;           // uniform force (FORCE_UNIFORM)
     float mw[d3q19::Q];         // 6 w_i (e_i . u_wall), rho_wall = 1
+    float uw[3];                // wall velocity (velocity of moving on-site nodes)
 };
 
 struct Launch {
@@ -28,10 +29,11 @@ Launch make_launch(const d3q19::Dims& d, int bx, int by, hipStream_t s);
 // One step. AB: reads `a`, writes `b`. AA: in place on `a`; parity 0 is the
 // gather/scatter step, parity 1 the local step.
 // AB only: rho/u non-null also stores the in-step rho [N] and u [3][N].
+// onsite: the lattice has on-site velocity nodes (rebuilt when collide).
 hipError_t launch_step(int storage, int pattern, int parity, bool collide, int force_mode,
                        void* a, void* b, const uint8_t* flags, const float* ffield,
                        const StepArgs& args, const Launch& L, float* rho = nullptr,
-                       float* u = nullptr);
+                       float* u = nullptr, bool onsite = false);
 
 // One AB step with vw consecutive x-points per work-item: vw = 4 (FP32,
 // 16-byte accesses; or 16-bit storage, 8-byte accesses) or vw = 8 (16-bit
@@ -41,13 +43,16 @@ bool vector_width_ok(int storage, int vw);
 hipError_t launch_step_abv(int storage, int vw, bool collide, int force_mode, void* a, void* b,
                            const uint8_t* flags, const uint32_t* smask, const uint32_t* mmask,
                            const float* ffield, const StepArgs& args, const Launch& L,
-                           float* rho = nullptr, float* u = nullptr);
+                           float* rho = nullptr, float* u = nullptr, bool onsite = false);
 
-// flags_out = type bits of flags_in plus NEAR_WALL / NEAR_MOVING on fluid
-// cells next to a solid / moving-wall cell; smask / mmask bit i set when
-// x - e_i is solid / a moving wall.
+// flags_in holds the caller's values 0..4 (fluid, wall, moving wall, on-site
+// node at rest, on-site node moving with u_w). flags_out = type bits (on-site
+// nodes are fluid) plus NEAR_WALL / NEAR_MOVING on fluid cells next to a
+// solid / moving-wall cell and ONSITE / ONSITE_MOVING; smask / mmask bit i
+// set when x - e_i is solid / a moving wall. *bad |= 1 for an on-site node
+// whose solid neighbours do not form a box face, edge or corner.
 hipError_t launch_mark_near_wall(const uint8_t* flags_in, uint8_t* flags_out, uint32_t* smask,
-                                 uint32_t* mmask, const d3q19::Dims& d, const Launch& L);
+                                 uint32_t* mmask, int* bad, const d3q19::Dims& d, const Launch& L);
 
 // f = f^eq(rho, u) in the given storage (natural layout).
 hipError_t launch_init_eq(int storage, void* f, const float* rho, const float* u,

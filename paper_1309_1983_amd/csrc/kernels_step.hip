@@ -38,9 +38,12 @@ __device__ __forceinline__ void load_force(const StepArgs& a, const float* __res
     }
 }
 
-// Decode, add moving-wall terms, collide. h ends as post-collision offsets.
-template <class St, int FM>
+// Decode, add moving-wall terms, rebuild the unknowns of an on-site node
+// (onsiteU != 0: its solid-source directions), collide. h ends as
+// post-collision offsets.
+template <class St, int FM, bool ONSITE>
 __device__ __forceinline__ Macro decode_collide(const typename St::raw_t raw[Q], uint32_t mwmask,
+                                                uint32_t onsiteU, bool onsite_moving,
                                                 const StepArgs& a, const float* __restrict__ ff,
                                                 uint32_t c, float h[Q])
 {
@@ -51,6 +54,12 @@ __device__ __forceinline__ Macro decode_collide(const typename St::raw_t raw[Q],
     }
     float Fx, Fy, Fz;
     load_force<FM>(a, ff, c, Fx, Fy, Fz);
+    if (ONSITE && onsiteU) {
+        const float ux = onsite_moving ? a.uw[0] : 0.0f;
+        const float uy = onsite_moving ? a.uw[1] : 0.0f;
+        const float uz = onsite_moving ? a.uw[2] : 0.0f;
+        onsite_rebuild<FM != FORCE_NONE>(h, onsiteU, ux, uy, uz, Fx, Fy, Fz);
+    }
     return bgk_collide<FM != FORCE_NONE>(h, a.omega, a.cF, Fx, Fy, Fz);
 }
 
@@ -68,8 +77,9 @@ __device__ __forceinline__ Macro decode_collide(const typename St::raw_t raw[Q],
 // bounce back at solid neighbours, collide, store into `dst`. Used when the
 // row length is not a multiple of the vector width. MACROS: also store the
 // in-step rho and u (the four extra stores per point of Section 4.1).
+// ONSITE: rebuild the unknown populations of on-site velocity nodes.
 // ---------------------------------------------------------------------------
-template <class St, int FM, bool COLLIDE, bool MACROS>
+template <class St, int FM, bool COLLIDE, bool MACROS, bool ONSITE>
 __global__ __launch_bounds__(1024) void k_step_ab(const typename St::raw_t* __restrict__ src,
                                                   typename St::raw_t* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
@@ -94,12 +104,13 @@ __global__ __launch_bounds__(1024) void k_step_ab(const typename St::raw_t* __re
 #pragma unroll
     for (int i = 0; i < Q; ++i) raw[i] = ld(plane(src, d, i, src_slab(i, z, zm, zp)), on[i]);
 
-    uint32_t mwmask = 0;
+    uint32_t mwmask = 0, solid = 0;
     if (fl & NEAR_WALL) {
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const uint8_t nf = flags[src_slab(i, z, zm, zp) * d.nxy + on[i]];
             if (nf & TYPE_MASK) {
+                solid |= 1u << i;
                 raw[i] = ld(plane(src, d, OPP[i], z), o);
                 if (nf & MOVING) mwmask |= 1u << i;
             }
@@ -112,7 +123,8 @@ __global__ __launch_bounds__(1024) void k_step_ab(const typename St::raw_t* __re
         return;
     }
     float h[Q];
-    const Macro m = decode_collide<St, FM>(raw, mwmask, a, ff, c, h);
+    const Macro m = decode_collide<St, FM, ONSITE>(raw, mwmask, (fl & ONSITE_NODE) ? solid : 0u,
+                                                   (fl & ONSITE_MOVING) != 0, a, ff, c, h);
 #pragma unroll
     for (int i = 0; i < Q; ++i) st(plane(dst, d, i, z), o, St::enc(h[i], i));
     if (MACROS) {
@@ -131,6 +143,8 @@ __global__ __launch_bounds__(1024) void k_step_ab(const typename St::raw_t* __re
 // HBM traffic does not grow). Near-wall points take the bounced values
 // s_opp(i)(x) through the precomputed solid-neighbour mask.
 // Solid points inside a work-item's group are written as the rest state.
+// ONSITE: on-site velocity nodes rebuild their unknowns (the solid-source
+// bits of the neighbour mask) before the collision.
 // Per fluid point the arithmetic is the one-point kernel's, bit for bit.
 // ---------------------------------------------------------------------------
 template <int VW>
@@ -146,7 +160,7 @@ struct FlagWord<8> {
     static constexpr uint64_t ones = 0x0101010101010101ull;
 };
 
-template <class St, int FM, bool COLLIDE, int VW, bool MACROS>
+template <class St, int FM, bool COLLIDE, int VW, bool MACROS, bool ONSITE>
 __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __restrict__ src,
                                                   typename St::bits_t* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
@@ -199,6 +213,15 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
             mm[4 * g] = m4.x; mm[4 * g + 1] = m4.y; mm[4 * g + 2] = m4.z; mm[4 * g + 3] = m4.w;
         }
     }
+    uint32_t os[VW];   // unknown-direction bits of on-site nodes, else 0
+#pragma unroll
+    for (int j = 0; j < VW; ++j) os[j] = 0u;
+    if (ONSITE && COLLIDE && (flw & (ONES * ONSITE_NODE))) {
+        load_words<VW>(smask, c0, os);
+#pragma unroll
+        for (int j = 0; j < VW; ++j)
+            if (!((flw >> (8 * j)) & ONSITE_NODE)) os[j] = 0u;
+    }
 
     if (COLLIDE) {
         float F[3][VW];
@@ -226,6 +249,11 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
             for (int i = 0; i < Q; ++i) {
                 h[i] = St::off_b(q[i][j], i);
                 if (i > 0 && ((mm[j] >> i) & 1u)) h[i] = h[i] + a.mw[i];
+            }
+            if (ONSITE && os[j]) {
+                const bool mv = (flw >> (8 * j)) & ONSITE_MOVING;
+                onsite_rebuild<FM != FORCE_NONE>(h, os[j], mv ? a.uw[0] : 0.0f, mv ? a.uw[1] : 0.0f,
+                                                 mv ? a.uw[2] : 0.0f, F[0][j], F[1][j], F[2][j]);
             }
             const Macro m = bgk_collide<FM != FORCE_NONE>(h, a.omega, a.cF, F[0][j], F[1][j], F[2][j]);
             const bool sol = (solid >> (8 * j)) & 1u;
@@ -259,7 +287,7 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
 // restoring the natural layout. Each work-item reads and writes the same 19
 // slots, and no two work-items share a slot, so the update is race-free.
 // ---------------------------------------------------------------------------
-template <class St, int FM, bool COLLIDE>
+template <class St, int FM, bool COLLIDE, bool ONSITE>
 __global__ __launch_bounds__(1024) void k_step_aa0(typename St::raw_t* f,
                                                    const uint8_t* __restrict__ flags,
                                                    const float* __restrict__ ff, StepArgs a)
@@ -290,7 +318,9 @@ __global__ __launch_bounds__(1024) void k_step_aa0(typename St::raw_t* f,
     }
 
     float h[Q];
-    if (COLLIDE) decode_collide<St, FM>(raw, mwmask, a, ff, c, h);
+    if (COLLIDE)
+        decode_collide<St, FM, ONSITE>(raw, mwmask, (fl & ONSITE_NODE) ? solid : 0u, (fl & ONSITE_MOVING) != 0,
+                                       a, ff, c, h);
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
         const int k = OPP[j];
@@ -300,7 +330,7 @@ __global__ __launch_bounds__(1024) void k_step_aa0(typename St::raw_t* f,
     }
 }
 
-template <class St, int FM, bool COLLIDE>
+template <class St, int FM, bool COLLIDE, bool ONSITE>
 __global__ __launch_bounds__(1024) void k_step_aa1(typename St::raw_t* f,
                                                    const uint8_t* __restrict__ flags,
                                                    const float* __restrict__ ff, StepArgs a)
@@ -315,13 +345,16 @@ __global__ __launch_bounds__(1024) void k_step_aa1(typename St::raw_t* f,
 #pragma unroll
     for (int i = 0; i < Q; ++i) raw[i] = ld(plane(f, d, OPP[i], z), o);
 
-    uint32_t mwmask = 0;
-    if (COLLIDE && (fl & NEAR_MOVING)) {
+    uint32_t mwmask = 0, solid = 0;
+    if (COLLIDE && ((fl & NEAR_MOVING) || (ONSITE && (fl & ONSITE_NODE)))) {
         uint32_t on[Q];
         pull_offsets(d, x, y, on);
 #pragma unroll
-        for (int i = 1; i < Q; ++i)
-            if ((flags[src_slab(i, z, zm, zp) * d.nxy + on[i]] & TYPE_MASK) == MOVING) mwmask |= 1u << i;
+        for (int i = 1; i < Q; ++i) {
+            const uint8_t t = flags[src_slab(i, z, zm, zp) * d.nxy + on[i]] & TYPE_MASK;
+            if (t == MOVING) mwmask |= 1u << i;
+            if (t) solid |= 1u << i;
+        }
     }
     if (!COLLIDE) {
 #pragma unroll
@@ -329,7 +362,8 @@ __global__ __launch_bounds__(1024) void k_step_aa1(typename St::raw_t* f,
         return;
     }
     float h[Q];
-    decode_collide<St, FM>(raw, mwmask, a, ff, c, h);
+    decode_collide<St, FM, ONSITE>(raw, mwmask, (fl & ONSITE_NODE) ? solid : 0u, (fl & ONSITE_MOVING) != 0, a,
+                                   ff, c, h);
 #pragma unroll
     for (int i = 0; i < Q; ++i) st(plane(f, d, i, z), o, St::enc(h[i], i));
 }
@@ -450,13 +484,19 @@ __global__ __launch_bounds__(1024) void k_check_finite(const typename St::raw_t*
     if (!ok) atomicOr(flag, 1);
 }
 
+// Caller flag value (0..4) -> type bits: only 1 (wall) and 2 (moving wall)
+// are solid; on-site nodes (3, 4) are fluid nodes.
+__device__ __forceinline__ uint8_t type_of(uint8_t v) { return (v == 1 || v == 2) ? v : 0; }
+
 __global__ __launch_bounds__(1024) void k_mark_near_wall(const uint8_t* __restrict__ in,
                                                          uint8_t* __restrict__ out,
                                                          uint32_t* __restrict__ smask,
-                                                         uint32_t* __restrict__ mmask, Dims d)
+                                                         uint32_t* __restrict__ mmask,
+                                                         int* __restrict__ bad, Dims d)
 {
     POINT_PROLOGUE(d)
-    const uint8_t fl = in[c] & TYPE_MASK;
+    const uint8_t v = in[c];
+    const uint8_t fl = type_of(v);
     uint8_t r = fl;
     uint32_t sm = 0, mm = 0;
     if (fl == 0) {
@@ -464,12 +504,17 @@ __global__ __launch_bounds__(1024) void k_mark_near_wall(const uint8_t* __restri
         pull_offsets(d, x, y, on);
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-            const uint8_t t = in[src_slab(i, z, zm, zp) * d.nxy + on[i]] & TYPE_MASK;
+            const uint8_t t = type_of(in[src_slab(i, z, zm, zp) * d.nxy + on[i]]);
             if (t) sm |= 1u << i;
             if (t == MOVING) mm |= 1u << i;
         }
         if (sm) r |= NEAR_WALL;
         if (mm) r |= NEAR_MOVING;
+        if (v >= 3) {
+            r |= ONSITE_NODE;
+            if (v == 4) r |= ONSITE_MOVING;
+            if (!onsite_pattern_ok(sm)) atomicOr(bad, 1);
+        }
     }
     out[c] = r;
     smask[c] = sm;
@@ -489,7 +534,7 @@ __global__ __launch_bounds__(256) void k_copy(const float* __restrict__ src, flo
 
 // ------------------------------- dispatch ----------------------------------
 
-template <class St, int FM>
+template <class St, int FM, bool ONSITE>
 static hipError_t step_fm(int pattern, int parity, bool collide, void* a, void* b,
                           const uint8_t* flags, const float* ff, const StepArgs& args,
                           const Launch& L, float* rho, float* u)
@@ -499,49 +544,59 @@ static hipError_t step_fm(int pattern, int parity, bool collide, void* a, void* 
     T* B = static_cast<T*>(b);
     if (pattern == 0) {
         if (collide && rho)
-            hipLaunchKernelGGL((k_step_ab<St, FM, true, true>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
+            hipLaunchKernelGGL((k_step_ab<St, FM, true, true, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
         else if (collide)
-            hipLaunchKernelGGL((k_step_ab<St, FM, true, false>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
+            hipLaunchKernelGGL((k_step_ab<St, FM, true, false, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
         else
-            hipLaunchKernelGGL((k_step_ab<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
+            hipLaunchKernelGGL((k_step_ab<St, FORCE_NONE, false, false, false>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
     } else if (parity == 0) {
         if (collide)
-            hipLaunchKernelGGL((k_step_aa0<St, FM, true>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
+            hipLaunchKernelGGL((k_step_aa0<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
         else
-            hipLaunchKernelGGL((k_step_aa0<St, FORCE_NONE, false>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
+            hipLaunchKernelGGL((k_step_aa0<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
     } else {
         if (collide)
-            hipLaunchKernelGGL((k_step_aa1<St, FM, true>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
+            hipLaunchKernelGGL((k_step_aa1<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
         else
-            hipLaunchKernelGGL((k_step_aa1<St, FORCE_NONE, false>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
+            hipLaunchKernelGGL((k_step_aa1<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
     }
     return hipGetLastError();
 }
 
-template <class St>
+template <class St, bool ONSITE>
 static hipError_t step_st(int pattern, int parity, bool collide, int fm, void* a, void* b,
                           const uint8_t* flags, const float* ff, const StepArgs& args,
                           const Launch& L, float* rho, float* u)
 {
     switch (fm) {
-    case FORCE_UNIFORM: return step_fm<St, FORCE_UNIFORM>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
-    case FORCE_FIELD: return step_fm<St, FORCE_FIELD>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
-    default: return step_fm<St, FORCE_NONE>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
+    case FORCE_UNIFORM: return step_fm<St, FORCE_UNIFORM, ONSITE>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
+    case FORCE_FIELD: return step_fm<St, FORCE_FIELD, ONSITE>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
+    default: return step_fm<St, FORCE_NONE, ONSITE>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
+    }
+}
+
+template <bool ONSITE>
+static hipError_t step_os(int storage, int pattern, int parity, bool collide, int force_mode, void* a,
+                          void* b, const uint8_t* flags, const float* ffield, const StepArgs& args,
+                          const Launch& L, float* rho, float* u)
+{
+    switch (storage) {
+    case 1: return step_st<StF16, ONSITE>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
+    case 2: return step_st<StBF16, ONSITE>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
+    default: return step_st<StF32, ONSITE>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
     }
 }
 
 hipError_t launch_step(int storage, int pattern, int parity, bool collide, int force_mode, void* a,
                        void* b, const uint8_t* flags, const float* ffield, const StepArgs& args,
-                       const Launch& L, float* rho, float* u)
+                       const Launch& L, float* rho, float* u, bool onsite)
 {
-    switch (storage) {
-    case 1: return step_st<StF16>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
-    case 2: return step_st<StBF16>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
-    default: return step_st<StF32>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
-    }
+    return (onsite && collide)
+               ? step_os<true>(storage, pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u)
+               : step_os<false>(storage, pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
 }
 
-template <class St, int FM, int VW>
+template <class St, int FM, int VW, bool ONSITE>
 static hipError_t stepv_fm(bool collide, void* a, void* b, const uint8_t* flags, const uint32_t* sm,
                            const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L,
                            float* rho, float* u)
@@ -550,46 +605,57 @@ static hipError_t stepv_fm(bool collide, void* a, void* b, const uint8_t* flags,
     const B* A = static_cast<const B*>(a);
     B* Bp = static_cast<B*>(b);
     if (collide && rho)
-        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, true>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, true, ONSITE>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     else if (collide)
-        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, false, ONSITE>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     else
-        hipLaunchKernelGGL((k_step_abv<St, FORCE_NONE, false, VW, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        hipLaunchKernelGGL((k_step_abv<St, FORCE_NONE, false, VW, false, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     return hipGetLastError();
 }
 
-template <class St, int VW>
+template <class St, int VW, bool ONSITE>
 static hipError_t stepv_st(bool collide, int fm, void* a, void* b, const uint8_t* flags, const uint32_t* sm,
                            const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L,
                            float* rho, float* u)
 {
     switch (fm) {
-    case FORCE_UNIFORM: return stepv_fm<St, FORCE_UNIFORM, VW>(collide, a, b, flags, sm, mm, ff, args, L, rho, u);
-    case FORCE_FIELD: return stepv_fm<St, FORCE_FIELD, VW>(collide, a, b, flags, sm, mm, ff, args, L, rho, u);
-    default: return stepv_fm<St, FORCE_NONE, VW>(collide, a, b, flags, sm, mm, ff, args, L, rho, u);
+    case FORCE_UNIFORM: return stepv_fm<St, FORCE_UNIFORM, VW, ONSITE>(collide, a, b, flags, sm, mm, ff, args, L, rho, u);
+    case FORCE_FIELD: return stepv_fm<St, FORCE_FIELD, VW, ONSITE>(collide, a, b, flags, sm, mm, ff, args, L, rho, u);
+    default: return stepv_fm<St, FORCE_NONE, VW, ONSITE>(collide, a, b, flags, sm, mm, ff, args, L, rho, u);
     }
 }
 
 bool vector_width_ok(int storage, int vw) { return vw == 4 || (vw == 8 && storage != 0); }
 
-hipError_t launch_step_abv(int storage, int vw, bool collide, int force_mode, void* a, void* b,
+template <bool ONSITE>
+static hipError_t stepv_os(int storage, int vw, bool collide, int force_mode, void* a, void* b,
                            const uint8_t* flags, const uint32_t* smask, const uint32_t* mmask,
                            const float* ffield, const StepArgs& args, const Launch& L, float* rho, float* u)
 {
     switch (storage * 16 + vw) {
-    case 1 * 16 + 8: return stepv_st<StF16, 8>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
-    case 1 * 16 + 4: return stepv_st<StF16, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
-    case 2 * 16 + 8: return stepv_st<StBF16, 8>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
-    case 2 * 16 + 4: return stepv_st<StBF16, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
-    case 0 * 16 + 4: return stepv_st<StF32, 4>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
+    case 1 * 16 + 8: return stepv_st<StF16, 8, ONSITE>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
+    case 1 * 16 + 4: return stepv_st<StF16, 4, ONSITE>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
+    case 2 * 16 + 8: return stepv_st<StBF16, 8, ONSITE>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
+    case 2 * 16 + 4: return stepv_st<StBF16, 4, ONSITE>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
+    case 0 * 16 + 4: return stepv_st<StF32, 4, ONSITE>(collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_mark_near_wall(const uint8_t* in, uint8_t* out, uint32_t* smask, uint32_t* mmask,
+hipError_t launch_step_abv(int storage, int vw, bool collide, int force_mode, void* a, void* b,
+                           const uint8_t* flags, const uint32_t* smask, const uint32_t* mmask,
+                           const float* ffield, const StepArgs& args, const Launch& L, float* rho, float* u,
+                           bool onsite)
+{
+    return (onsite && collide)
+               ? stepv_os<true>(storage, vw, collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u)
+               : stepv_os<false>(storage, vw, collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
+}
+
+hipError_t launch_mark_near_wall(const uint8_t* in, uint8_t* out, uint32_t* smask, uint32_t* mmask, int* bad,
                                  const Dims& d, const Launch& L)
 {
-    hipLaunchKernelGGL(k_mark_near_wall, L.grid, L.block, 0, L.stream, in, out, smask, mmask, d);
+    hipLaunchKernelGGL(k_mark_near_wall, L.grid, L.block, 0, L.stream, in, out, smask, mmask, bad, d);
     return hipGetLastError();
 }
 

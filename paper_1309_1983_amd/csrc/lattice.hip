@@ -69,6 +69,7 @@ struct lbm_lattice {
     int cpl = 1;                   // points per work-item of the AB step (1 or the vector width)
     bool vec_ok = true;            // vector kernels allowed (cells_per_lane != 1)
     int bx4 = 64, by4 = 1;         // work-group of the vector kernel
+    bool onsite = false;           // has on-site velocity nodes (flags 3, 4)
 
     bool sticky = false;
     long long steps_done = 0;
@@ -152,6 +153,7 @@ lbmk::StepArgs step_args(const lbm_lattice* L)
                           + d3q19::EZ[i] * (double)L->uw[2];
         a.mw[i] = (float)(6.0 * (double)d3q19::weight(i) * eu);
     }
+    for (int k = 0; k < 3; ++k) a.uw[k] = L->uw[k];
     return a;
 }
 
@@ -288,9 +290,12 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
         return fail(LBM_ERR_INVALID, "cells_per_lane = %d needs the AB pattern, nx %% %d == 0 and <= 256 work-items per group",
                     vw, vw);
     if (cpl > 1 && (ny + by4 - 1) / by4 > 65535) return fail(LBM_ERR_INVALID, "ny/block_y must be <= 65535 work-groups");
+    bool onsite = false;
     if (flags_host) {
-        for (unsigned long long c = 0; c < N; ++c)
-            if (flags_host[c] > 2) return fail(LBM_ERR_INVALID, "flag value %u at point %llu (allowed 0, 1, 2)", flags_host[c], c);
+        for (unsigned long long c = 0; c < N; ++c) {
+            if (flags_host[c] > 4) return fail(LBM_ERR_INVALID, "flag value %u at point %llu (allowed 0..4)", flags_host[c], c);
+            onsite = onsite || flags_host[c] >= 3;
+        }
     }
 
     int dev = opt.device;
@@ -316,6 +321,7 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
     L->check_interval = opt.check_interval;
     L->cpl = cpl;
     L->vec_ok = opt.cells_per_lane != 1;
+    L->onsite = onsite;
     if (cpl > 1) { L->bx4 = bx4; L->by4 = by4; }
 
     lbm_status st = LBM_OK;
@@ -333,7 +339,14 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
                                   : hipMemsetAsync(d_raw, 0, L->N, L->stream);
         st = hip_check(L, e, "flags upload");
     }
-    if (st == LBM_OK) st = hip_check(L, lbmk::launch_mark_near_wall(d_raw, L->d_flags, L->d_smask, L->d_mmask, L->dims, launch_of(L)), "mark_near_wall");
+    if (st == LBM_OK) st = hip_check(L, hipMemsetAsync(L->d_check, 0, sizeof(int), L->stream), "check flag clear");
+    if (st == LBM_OK)
+        st = hip_check(L, lbmk::launch_mark_near_wall(d_raw, L->d_flags, L->d_smask, L->d_mmask, L->d_check, L->dims,
+                                                      launch_of(L)), "mark_near_wall");
+    int bad_onsite = 0;
+    if (st == LBM_OK)
+        st = hip_check(L, hipMemcpyAsync(&bad_onsite, L->d_check, sizeof(int), hipMemcpyDeviceToHost, L->stream),
+                       "check flag read");
     // rest state in every array (solid points keep it forever)
     for (int b = 0; b < nbuf && st == LBM_OK; ++b)
         st = hip_check(L, lbmk::launch_init_eq(L->storage, L->d_f[b], nullptr, nullptr, L->dims, launch_of(L)), "init");
@@ -343,6 +356,9 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
             if (st == LBM_OK) st = hip_check(L, hipEventCreate(&ev), "hipEventCreate");
     }
     if (st == LBM_OK) st = hip_check(L, hipStreamSynchronize(L->stream), "create sync");
+    if (st == LBM_OK && bad_onsite)
+        st = fail(LBM_ERR_INVALID, "an on-site velocity node (flag 3 or 4) has solid neighbours that do not form "
+                                   "a box face, edge or corner");
     if (d_raw) dfree(L, d_raw, L->N);
     if (st != LBM_OK) {
         std::string msg = g_last_error;
@@ -597,6 +613,7 @@ lbm_status lbm_forward_checkpointed(lbm_lattice* L, int T, int K)
     if (T < 0 || K <= 0) return fail(LBM_ERR_INVALID, "need T >= 0 and K > 0 (got T=%d K=%d)", T, K);
     if (L->storage != LBM_STORAGE_F32 || L->pattern != LBM_PATTERN_AB)
         return fail(LBM_ERR_STATE, "the adjoint rollout needs F32 storage and the AB pattern");
+    if (L->onsite) return fail(LBM_ERR_STATE, "the adjoint does not cover on-site velocity nodes");
     DeviceGuard guard(L->device);
     drop_trajectory(L);
     const size_t sb = (size_t)Q * L->N * sizeof(float);
@@ -736,15 +753,15 @@ lbm_status run_steps(lbm_lattice* L, int n, bool collide, float* rho, float* u)
         float* mu = s == n - 1 ? u : nullptr;
         if (L->pattern == LBM_PATTERN_AB && L->cpl > 1) {
             HIPCHK(L, lbmk::launch_step_abv(L->storage, L->cpl, collide, fm, L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags,
-                                            L->d_smask, L->d_mmask, L->d_force, args, LA4, mr, mu));
+                                            L->d_smask, L->d_mmask, L->d_force, args, LA4, mr, mu, L->onsite));
             L->cur ^= 1;
         } else if (L->pattern == LBM_PATTERN_AB) {
             HIPCHK(L, lbmk::launch_step(L->storage, 0, 0, collide, fm, L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags,
-                                        L->d_force, args, LA, mr, mu));
+                                        L->d_force, args, LA, mr, mu, L->onsite));
             L->cur ^= 1;
         } else {
             HIPCHK(L, lbmk::launch_step(L->storage, 1, L->parity, collide, fm, L->d_f[0], nullptr, L->d_flags,
-                                        L->d_force, args, LA));
+                                        L->d_force, args, LA, nullptr, nullptr, L->onsite));
             L->parity ^= 1;
         }
         ++L->steps_done;

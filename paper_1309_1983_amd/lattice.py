@@ -25,7 +25,8 @@ def _ptr(t: torch.Tensor | None):
 class Lattice:
     """nx*ny*nz D3Q19 lattice (index c = (z*ny + y)*nx + x, populations [19][N]).
 
-    flags: uint8 per point (0 fluid, 1 wall, 2 moving wall) as numpy / torch /
+    flags: uint8 per point (0 fluid, 1 wall, 2 moving wall, 3 on-site velocity
+    node at rest, 4 on-site node moving with the wall velocity) as numpy / torch /
     None (all fluid). storage: 'f32' | 'f16' | 'bf16' (16-bit offsets).
     pattern: 'ab' (two arrays) | 'aa' (one array, in place).
     """

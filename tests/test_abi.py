@@ -90,9 +90,9 @@ def test_create_rejects_bad_arguments(abi, dims, tau, msg):
 
 def test_create_rejects_bad_flags_and_options(abi):
     flags = np.zeros(64, dtype=np.uint8)
-    flags[17] = 3
+    flags[17] = 5
     st, _ = _create(abi, 4, 4, 4, 0.8, flags)
-    assert st == abi.LBM_ERR_INVALID and "flag value 3" in abi.last_error()
+    assert st == abi.LBM_ERR_INVALID and "flag value 5" in abi.last_error()
     for field, value in (("storage", 3), ("pattern", 2), ("block_x", 2048), ("block_y", -1),
                          ("timing_capacity", -5)):
         opt = abi.lbm_options()
