@@ -76,10 +76,10 @@ def time_steps(lat, steps, torch):
     return e0.elapsed_time(e1) / steps
 
 
-def cavity_lattice(n, storage, pattern, tau, lid, block=None, cells_per_lane=0):
+def cavity_lattice(n, storage, pattern, tau, lid, block=None, cells_per_lane=0, onsite=False):
     import workloads as W
     from paper_1309_1983_amd import Lattice
-    flags = W.cavity_flags(n, n, n)
+    flags = W.onsite_cavity_flags(n, n, n) if onsite else W.cavity_flags(n, n, n)
     lat = Lattice(n, n, n, tau, flags=flags, storage=storage, pattern=pattern, block=block,
                   cells_per_lane=cells_per_lane)
     lat.set_wall_velocity(lid)
@@ -265,6 +265,9 @@ def main():
     ap.add_argument("--timing-steps", type=int, default=10000)
     ap.add_argument("--study", action="store_true",
                     help="run the memory-access study (Section 4.3 experiments) instead")
+    ap.add_argument("--cavity", action="store_true",
+                    help="run the cavity validation (Section 5: Re 100, 400, 1000 with on-site "
+                         "walls, Eq. (8) scaling, doubled resolutions) instead")
     ap.add_argument("--copy-only", action="store_true",
                     help="run only the copy probe (2 GiB float32, 20 launches): counter calibration")
     args = ap.parse_args()
@@ -281,6 +284,20 @@ def main():
 
     if args.study:
         print(json.dumps({"study": access_study(torch, args.n)}), flush=True)
+        return
+
+    if args.cavity:
+        from paper_1309_1983_amd import cavity
+        out = cavity.validation(log=sys.stderr)
+        summary = {}
+        for Re, v in out.items():
+            summary[str(Re)] = {
+                "runs": [{k: r.as_dict()[k] for k in ("L", "tau", "u_lid", "steps", "converged", "residual",
+                                                      "finite", "seconds", "glups")} for r in v["runs"]],
+                "max_profile_differences": v["differences"], "observed_orders": v["orders"],
+                "finest": {k: v["runs"][-1].as_dict()[k] for k in ("L", "y", "ux", "x", "uy")},
+            }
+        print(json.dumps({"cavity_validation": summary}), flush=True)
         return
 
     if args.copy_only:
@@ -326,7 +343,8 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "bytes_per_point": BYTES_PER_POINT["f32"],
-                     "kernel": ("k_step_ab4" if n % 4 == 0 else "k_step_ab") + "<StF32, FORCE_NONE, collide>"},
+                     "kernel": ("k_step_abv<StF32, FORCE_NONE, COLLIDE, VW=4>" if n % 4 == 0
+                                else "k_step_ab<StF32, FORCE_NONE, COLLIDE>")},
     }
     log(f"FP32 AB: {ms:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
@@ -351,6 +369,17 @@ def main():
                           "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                           "bytes_per_point": bpp}
             log(f"{key}: {m:.4f} ms/step, {N / m / 1e3:.0f} MLUPS, {gbs:.0f} GB/s")
+        # the cavity closed by on-site velocity walls (the paper's validation boundaries)
+        lat = cavity_lattice(n, "f32", "ab", tau, lid, onsite=True)
+        lat.step(args.warmup)
+        m = time_steps(lat, args.steps, torch)
+        lat.check_finite()
+        lat.close()
+        gbs = BYTES_PER_POINT["f32"] * N / (m * 1e-3) / 1e9
+        extra["f32_ab_onsite_walls"] = {"mlups": round(N / m / 1e3, 1), "ms_per_step": round(m, 5),
+                                        "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                        "bytes_per_point": BYTES_PER_POINT["f32"]}
+        log(f"f32_ab on-site walls: {m:.4f} ms/step, {N / m / 1e3:.0f} MLUPS, {gbs:.0f} GB/s")
         # the step with rho and u stored every step (four extra stores per point)
         lat = cavity_lattice(n, "f32", "ab", tau, lid)
         lat.step(args.warmup)

@@ -1,0 +1,48 @@
+"""Host-side pieces of the cavity validation workload (Section 5): the
+geometry, the Eq. (8) scaling and the resolution comparison."""
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_1309_1983_amd import cavity
+
+
+@pytest.mark.parametrize("L", [2, 8, 16])
+def test_cavity_geometry_is_the_onsite_cavity(L):
+    n = L + 3
+    np.testing.assert_array_equal(cavity.cavity_flags(L), W.onsite_cavity_flags(n, n, n))
+    f = cavity.cavity_flags(L).reshape(n, n, n)
+    assert np.all(f[1:-1, L + 1, 1:-1] == W.ONSITE_MOVING)      # the lid, edges included
+    assert np.count_nonzero(f == W.ONSITE) + np.count_nonzero(f == W.ONSITE_MOVING) \
+        == (L + 1) ** 3 - (L - 1) ** 3
+
+
+def test_odd_side_is_rejected():
+    with pytest.raises(ValueError):
+        cavity.cavity_flags(15)
+
+
+@pytest.mark.parametrize("Re,L,u", [(100, 64, 0.1), (400, 128, 0.05), (1000, 256, 0.1)])
+def test_eq8_scaling(Re, L, u):
+    tau = cavity.tau_for(Re, L, u)
+    assert u == pytest.approx((tau - 0.5) * Re / (3 * L), rel=1e-14)
+    nu = (tau - 0.5) / 3
+    assert u * L / nu == pytest.approx(Re, rel=1e-12)
+
+
+def _result(L, ux, uy):
+    pos = np.arange(L + 1) / L
+    return cavity.CavityResult(Re=100, L=L, tau=0.6, u_lid=0.1, steps=1, converged=True, residual=0.0,
+                               finite=True, y=pos, ux=ux, x=pos, uy=uy, seconds=1.0, glups=1.0)
+
+
+def test_resolution_differences_recover_the_order_of_a_known_error():
+    # profiles = exact + C h^2 on each grid: differences shrink 4x per doubling
+    exact = lambda s: np.sin(np.pi * s)
+    res = []
+    for L in (8, 16, 32):
+        s = np.arange(L + 1) / L
+        res.append(_result(L, exact(s) + 0.3 * (1.0 / L) ** 2 * np.cos(s), exact(s)))
+    diffs, orders = cavity.resolution_differences(res)
+    assert diffs[0] > diffs[1] > 0
+    assert orders[0] == pytest.approx(2.0, abs=1e-9)
