@@ -294,7 +294,9 @@ def main():
             summary[str(Re)] = {
                 "runs": [{k: r.as_dict()[k] for k in ("L", "tau", "u_lid", "steps", "converged", "residual",
                                                       "finite", "seconds", "glups")} for r in v["runs"]],
+                "fixed": v["fixed"],
                 "max_profile_differences": v["differences"], "observed_orders": v["orders"],
+                "rms_profile_differences": v["rms_differences"], "rms_orders": v["rms_orders"],
                 "finest": {k: v["runs"][-1].as_dict()[k] for k in ("L", "y", "ux", "x", "uy")},
             }
         print(json.dumps({"cavity_validation": summary}), flush=True)

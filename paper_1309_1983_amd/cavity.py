@@ -5,11 +5,16 @@ Every face of the cube is a wall of on-site velocity nodes; the nodes of the
 top face (y = L, edges and corners included) move with the lid along +x, all
 others are at rest. The walls lie on node planes, so a cavity of side L
 lattice spacings has L + 1 nodes per side; one layer of solid cells outside
-closes the box (L + 3 points per side in all).
+closes the box (L + 3 points per side in all, plus solid padding along x up
+to a multiple of 4 points so that the vector step kernel applies).
 
 Eq. (8) ties the lid speed u, the relaxation time tau, the Reynolds number Re
 and the side L: u = (tau - 1/2) Re / (3 L), i.e. Re = u L / nu with
-nu = (tau - 1/2) / 3. `run` fixes u and L and takes tau from Re.
+nu = (tau - 1/2) / 3. `run` takes Re, L and either u or tau.
+
+With the on-site walls read as here, the scheme loses stability near
+tau = 0.55 at these resolutions (the lid corners go first), so high Reynolds
+numbers need large L, as in the paper.
 
 The result holds the two centreline profiles used to validate the solver
 (Section 5): u_x along the vertical line through the cavity centre
@@ -35,18 +40,27 @@ def tau_for(Re: float, L: int, u_lid: float) -> float:
     return 0.5 + 3.0 * u_lid * L / Re
 
 
+def lid_speed_for(Re: float, L: int, tau: float) -> float:
+    """Lid speed from Eq. (8): u = (tau - 1/2) Re / (3 L)."""
+    return (tau - 0.5) * Re / (3.0 * L)
+
+
+def box_shape(L: int):
+    """(nx, ny, nz) of the cavity of side L."""
+    n = L + 3
+    return (n + 3) // 4 * 4, n, n
+
+
 def cavity_flags(L: int) -> np.ndarray:
-    """Flags of the cavity of side L (even): (L+3)^3 points, x fastest."""
+    """Flags of the cavity of side L (even), x fastest: on-site walls on the
+    node planes 1 and L + 1 of every axis, solid outside."""
     if L < 2 or L % 2:
         raise ValueError(f"cavity side must be even and >= 2 (got {L})")
-    n = L + 3
-    f = np.zeros((n, n, n), dtype=np.uint8)      # [z][y][x]
-    f[1:-1, 1:-1, 1:-1] = ONSITE
-    f[2:-2, 2:-2, 2:-2] = 0
-    f[1:-1, -2, 1:-1] = ONSITE_MOVING
-    f[0, :, :] = f[-1, :, :] = WALL
-    f[:, 0, :] = f[:, -1, :] = WALL
-    f[:, :, 0] = f[:, :, -1] = WALL
+    nx, n, _ = box_shape(L)
+    f = np.full((n, n, nx), WALL, dtype=np.uint8)      # [z][y][x]
+    f[1:-1, 1:-1, 1:n - 1] = ONSITE
+    f[2:-2, 2:-2, 2:n - 2] = 0
+    f[1:-1, -2, 1:n - 1] = ONSITE_MOVING
     return f.reshape(-1)
 
 
@@ -65,7 +79,7 @@ class CavityResult:
     x: np.ndarray              # positions / L of the horizontal centreline
     uy: np.ndarray             # u_y / u_lid along it
     seconds: float
-    glups: float               # lattice updates per second / 1e9 (all (L+3)^3 points)
+    glups: float               # lattice updates per second / 1e9 (all points of the box)
 
     def as_dict(self):
         d = dataclasses.asdict(self)
@@ -75,26 +89,34 @@ class CavityResult:
 
 
 def _profiles(lat: Lattice, L: int, u_lid: float):
-    n = L + 3
+    nx, n, _ = box_shape(L)
     m = 1 + L // 2
     _, u = lat.macros()
-    u = u.reshape(3, n, n, n)                      # [c][z][y][x]
+    u = u.reshape(3, n, n, nx)                     # [c][z][y][x]
     ux = (u[0, m, 1:L + 2, m] / u_lid).double().cpu().numpy()
     uy = (u[1, m, m, 1:L + 2] / u_lid).double().cpu().numpy()
     return ux, uy
 
 
-def run(Re: float, L: int, u_lid: float = 0.1, storage: str = "f32", tol: float = 1e-5,
-        check_every: int | None = None, max_steps: int | None = None, log=None) -> CavityResult:
+def run(Re: float, L: int, u_lid: float | None = None, tau: float | None = None,
+        storage: str = "f32", tol: float = 1e-5, check_every: int | None = None,
+        max_steps: int | None = None, log=None) -> CavityResult:
     """Runs the cavity from rest until the scaled centreline profiles change
     by less than `tol` between two checks `check_every` steps apart (default
     2L), or until `max_steps` (default 80 L / u_lid, i.e. 80 lid transit
-    times). `log`: file for one progress line per check."""
-    tau = tau_for(Re, L, u_lid)
-    n = L + 3
+    times). Give the lid speed or tau (Eq. (8) gives the other; default lid
+    speed 0.1). `log`: file for one progress line per check."""
+    if u_lid is not None and tau is not None:
+        raise ValueError("give u_lid or tau, not both")
+    if tau is None:
+        u_lid = 0.1 if u_lid is None else u_lid
+        tau = tau_for(Re, L, u_lid)
+    else:
+        u_lid = lid_speed_for(Re, L, tau)
+    nx, n, _ = box_shape(L)
     check_every = check_every or max(2 * L, 100)
     max_steps = max_steps or int(80 * L / u_lid)
-    lat = Lattice(n, n, n, tau, flags=cavity_flags(L), storage=storage)
+    lat = Lattice(nx, n, n, tau, flags=cavity_flags(L), storage=storage)
     try:
         lat.set_wall_velocity(u_lid, 0.0, 0.0)
         prev_x, prev_y = _profiles(lat, L, u_lid)
@@ -123,20 +145,21 @@ def run(Re: float, L: int, u_lid: float = 0.1, storage: str = "f32", tol: float 
     pos = np.arange(L + 1) / L
     return CavityResult(Re=Re, L=L, tau=tau, u_lid=u_lid, steps=steps, converged=converged,
                         residual=residual, finite=finite, y=pos, ux=prev_x, x=pos, uy=prev_y,
-                        seconds=secs, glups=n ** 3 * steps / secs / 1e9)
+                        seconds=secs, glups=nx * n * n * steps / secs / 1e9)
 
 
-def resolution_differences(results):
-    """Max differences of the scaled centreline profiles between successive
-    resolutions (L, 2L, ...), compared at the coarse nodes, and the observed
-    order log2(d_k / d_{k+1})."""
+def resolution_differences(results, norm="max"):
+    """Differences of the scaled centreline profiles between successive
+    resolutions (L, 2L, ...), compared at the coarse nodes, in the max norm or
+    the root-mean-square ("rms") over both profiles, and the observed orders
+    log2(d_k / d_{k+1})."""
     rs = sorted(results, key=lambda r: r.L)
     diffs = []
     for a, b in zip(rs, rs[1:]):
         if b.L != 2 * a.L:
             raise ValueError("resolutions must double")
-        d = max(np.max(np.abs(a.ux - b.ux[::2])), np.max(np.abs(a.uy - b.uy[::2])))
-        diffs.append(float(d))
+        e = np.concatenate([a.ux - b.ux[::2], a.uy - b.uy[::2]])
+        diffs.append(float(np.max(np.abs(e)) if norm == "max" else np.sqrt(np.mean(e * e))))
     orders = [float(np.log2(d0 / d1)) for d0, d1 in zip(diffs, diffs[1:]) if d1 > 0]
     return diffs, orders
 
@@ -154,13 +177,24 @@ def _finite_doubling_runs(res):
     return chain
 
 
-def validation(Re_list=(100, 400, 1000), sides=None, u_lid=0.1, log=sys.stderr):
-    """The paper's three Reynolds numbers at successively doubled sides."""
-    sides = sides or {100: (32, 64, 128), 400: (64, 128, 256), 1000: (64, 128, 256)}
+# (Re, sides, fixed parameter): diffusive scaling (tau fixed, u ~ 1/L) where
+# the lid speed stays at or below about 0.1, else a fixed lid speed.
+VALIDATION_CASES = (
+    (100, (32, 64, 128), {"tau": 0.6}),
+    (400, (128, 256), {"tau": 0.6}),
+    (1000, (256,), {"u_lid": 0.1}),
+)
+
+
+def validation(cases=VALIDATION_CASES, log=sys.stderr):
+    """The paper's three Reynolds numbers, each at doubled sides where the
+    cost allows."""
     out = {}
-    for Re in Re_list:
-        res = [run(Re, L, u_lid=u_lid, log=log) for L in sides[Re]]
+    for Re, sides, fixed in cases:
+        res = [run(Re, L, log=log, **fixed) for L in sides]
         chain = _finite_doubling_runs(res)
         diffs, orders = resolution_differences(chain) if len(chain) > 1 else ([], [])
-        out[Re] = {"runs": res, "differences": diffs, "orders": orders}
+        rms, rms_orders = resolution_differences(chain, "rms") if len(chain) > 1 else ([], [])
+        out[Re] = {"runs": res, "differences": diffs, "orders": orders, "rms_differences": rms,
+                   "rms_orders": rms_orders, "fixed": fixed}
     return out

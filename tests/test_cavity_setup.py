@@ -7,12 +7,16 @@ import workloads as W
 from paper_1309_1983_amd import cavity
 
 
-@pytest.mark.parametrize("L", [2, 8, 16])
+@pytest.mark.parametrize("L", [2, 8, 16, 18])
 def test_cavity_geometry_is_the_onsite_cavity(L):
     n = L + 3
-    np.testing.assert_array_equal(cavity.cavity_flags(L), W.onsite_cavity_flags(n, n, n))
-    f = cavity.cavity_flags(L).reshape(n, n, n)
-    assert np.all(f[1:-1, L + 1, 1:-1] == W.ONSITE_MOVING)      # the lid, edges included
+    nx, ny, nz = cavity.box_shape(L)
+    assert nx % 4 == 0 and nx - n < 4 and ny == nz == n
+    f = cavity.cavity_flags(L).reshape(n, n, nx)
+    ref = W.onsite_cavity_flags(n, n, n).reshape(n, n, n)
+    np.testing.assert_array_equal(f[:, :, :n], ref)
+    assert np.all(f[:, :, n:] == W.WALL)                         # padding along x is solid
+    assert np.all(f[1:-1, L + 1, 1:n - 1] == W.ONSITE_MOVING)   # the lid, edges included
     assert np.count_nonzero(f == W.ONSITE) + np.count_nonzero(f == W.ONSITE_MOVING) \
         == (L + 1) ** 3 - (L - 1) ** 3
 
@@ -26,6 +30,7 @@ def test_odd_side_is_rejected():
 def test_eq8_scaling(Re, L, u):
     tau = cavity.tau_for(Re, L, u)
     assert u == pytest.approx((tau - 0.5) * Re / (3 * L), rel=1e-14)
+    assert cavity.lid_speed_for(Re, L, tau) == pytest.approx(u, rel=1e-14)
     nu = (tau - 0.5) / 3
     assert u * L / nu == pytest.approx(Re, rel=1e-12)
 

