@@ -398,15 +398,6 @@ __device__ __forceinline__ uint32_t opp_bits(uint32_t m)
     return ((m & 0x2AAAAu) << 1) | ((m & 0x55554u) >> 1);
 }
 
-// Direction bits with a non-zero x, y or z component.
-constexpr uint32_t axis_bits(int axis)
-{
-    uint32_t b = 0;
-    for (int i = 0; i < Q; ++i)
-        if ((axis == 0 ? EX[i] : (axis == 1 ? EY[i] : EZ[i])) != 0) b |= 1u << i;
-    return b;
-}
-
 // U is a valid unknown set: the union over one to three axis-aligned walls of
 // the directions pointing away from that wall (box face, edge or corner).
 __device__ __forceinline__ bool onsite_pattern_ok(uint32_t U)
@@ -426,25 +417,39 @@ __device__ __forceinline__ bool onsite_pattern_ok(uint32_t U)
 }
 
 // h: offsets after the gather (entries in U arbitrary) -> rebuilt offsets.
+// Written without branches (per-direction selects): the unknown set differs
+// from lane to lane, and branches would serialise.
+// With the wall normals n_k (unit vectors pointing into the fluid, one to
+// three of them) the class constants follow from the velocity set:
+//   a = 6 sum_{bounced} w_i e_i = c_k sum_k n_k, c = 1, 5/6, 2/3 for a face,
+//   edge, corner (the directions shared by two walls are buried);
+//   W_B = (number of buried directions) / 36;
+//   bounced links with a non-zero component along a tangential axis: 2 on a
+//   face, 4 on an edge (none on a corner).
 template <bool FORCE>
 __device__ __forceinline__ void onsite_rebuild(float h[Q], uint32_t U, float ux, float uy, float uz,
                                                float Fx, float Fy, float Fz)
 {
     const uint32_t Bm = U & opp_bits(U);   // buried pairs
     const uint32_t Rm = U & ~Bm;           // bounced unknowns
+    const float nx = (U & 2u) ? 1.0f : ((U & 4u) ? -1.0f : 0.0f);
+    const float ny = (U & 8u) ? 1.0f : ((U & 16u) ? -1.0f : 0.0f);
+    const float nz = (U & 32u) ? 1.0f : ((U & 64u) ? -1.0f : 0.0f);
+    const bool tx = nx == 0.0f, ty = ny == 0.0f, tz = nz == 0.0f;
+    const int walls = 3 - (int)tx - (int)ty - (int)tz;
+    const float ca = walls == 1 ? 1.0f : (walls == 2 ? 5.0f / 6.0f : 2.0f / 3.0f);
+    const float ax = ca * nx, ay = ca * ny, az = ca * nz;
+    const float WB = (float)__builtin_popcount(Bm) * (1.0f / 36.0f);
     const float usq = fmaf(ux, ux, fmaf(uy, uy, uz * uz));
-    float H = 0.0f, ax = 0.0f, ay = 0.0f, az = 0.0f, WB = 0.0f, Bq = 0.0f;
+    float H = h[0], Bq = 0.0f;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const bool rb = (Rm >> i) & 1u, bu = (Bm >> i) & 1u;
-        H += bu ? 0.0f : (rb ? h[OPP[i]] : h[i]);
-        const float w6 = 6.0f * weight(i);
-        ax += rb ? w6 * (float)EX[i] : 0.0f;
-        ay += rb ? w6 * (float)EY[i] : 0.0f;
-        az += rb ? w6 * (float)EZ[i] : 0.0f;
-        const float eu = edot(i, ux, uy, uz);
-        WB += bu ? weight(i) : 0.0f;
-        Bq += bu ? weight(i) * fmaf(4.5f * eu, eu, -1.5f * usq) : 0.0f;
+    for (int i = 1; i < Q; ++i) {
+        const bool unknown = (U >> i) & 1u, rb = (Rm >> i) & 1u;
+        H += unknown ? (rb ? h[OPP[i]] : 0.0f) : h[i];
+        if (i >= 7) {   // only diagonal directions can be buried
+            const float eu = edot(i, ux, uy, uz);
+            Bq += ((Bm >> i) & 1u) ? weight(i) * fmaf(4.5f * eu, eu, -1.5f * usq) : 0.0f;
+        }
     }
     const float au = fmaf(ax, ux, fmaf(ay, uy, az * uz));
     float num = H + au + Bq;
@@ -460,26 +465,23 @@ __device__ __forceinline__ void onsite_rebuild(float h[Q], uint32_t U, float ux,
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const float w = weight(i);
-        if ((Rm >> i) & 1u) {
-            h[i] = fmaf(6.0f * w, edot(i, jx, jy, jz), h[OPP[i]]);
-        } else if ((Bm >> i) & 1u) {
+        const float vr = fmaf(6.0f * w, edot(i, jx, jy, jz), h[OPP[i]]);
+        float v = ((Rm >> i) & 1u) ? vr : h[i];
+        if (i >= 7) {
             const float eu = edot(i, ux, uy, uz);
-            float v = w * fmaf(rho, fmaf(eu, fmaf(4.5f, eu, 3.0f), -1.5f * usq), delta);
-            if (FORCE) v = fmaf(-1.5f * w, edot(i, Fx, Fy, Fz), v);
-            h[i] = v;
+            float vb = w * fmaf(rho, fmaf(eu, fmaf(4.5f, eu, 3.0f), -1.5f * usq), delta);
+            if (FORCE) vb = fmaf(-1.5f * w, edot(i, Fx, Fy, Fz), vb);
+            v = ((Bm >> i) & 1u) ? vb : v;
         }
+        h[i] = v;
     }
-    // tangential momentum remainder
-    const bool tx = (U & 0x6u) == 0, ty = (U & 0x18u) == 0, tz = (U & 0x60u) == 0;
-    const int nx = __builtin_popcount(Rm & axis_bits(0));
-    const int ny = __builtin_popcount(Rm & axis_bits(1));
-    const int nz = __builtin_popcount(Rm & axis_bits(2));
-    const float lx = (tx && nx > 0) ? (jx - mom_x(h)) / (float)nx : 0.0f;
-    const float ly = (ty && ny > 0) ? (jy - mom_y(h)) / (float)ny : 0.0f;
-    const float lz = (tz && nz > 0) ? (jz - mom_z(h)) / (float)nz : 0.0f;
+    // tangential momentum remainder (spread over 2 or 4 links: exact scaling)
+    const float inv_n = walls == 1 ? 0.5f : 0.25f;
+    const float lx = tx ? (jx - mom_x(h)) * inv_n : 0.0f;
+    const float ly = ty ? (jy - mom_y(h)) * inv_n : 0.0f;
+    const float lz = tz ? (jz - mom_z(h)) * inv_n : 0.0f;
 #pragma unroll
-    for (int i = 1; i < Q; ++i)
-        if ((Rm >> i) & 1u) h[i] += edot(i, lx, ly, lz);
+    for (int i = 1; i < Q; ++i) h[i] += ((Rm >> i) & 1u) ? edot(i, lx, ly, lz) : 0.0f;
 }
 
 // Returns the in-step macroscopic values (rho, u = (m + F/2)/rho).

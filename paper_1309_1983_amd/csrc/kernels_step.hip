@@ -241,6 +241,40 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
                 F[2][j] = FM == FORCE_UNIFORM ? a.Fz : 0.0f;
             }
         }
+        // On-site nodes: the first on-site point of each work-item is rebuilt
+        // before the loop, so a wave whose on-site points sit at different
+        // positions in different work-items (the two ends of a row) runs the
+        // rebuild once rather than once per position; further on-site points
+        // of a work-item (rows lying on a face of the box) are rebuilt in the
+        // loop. The moving-wall terms are skipped for that point: they only
+        // touch its unknown directions, which the rebuild overwrites.
+        int jr = VW;
+        float hr[ONSITE ? Q : 1];
+        if (ONSITE) {
+            uint32_t Ur = 0u;
+#pragma unroll
+            for (int j = VW - 1; j >= 0; --j)
+                if (os[j]) { jr = j; Ur = os[j]; }
+            if (Ur) {
+                float fr[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    fr[k] = F[k][0];
+#pragma unroll
+                    for (int j = 1; j < VW; ++j) fr[k] = jr == j ? F[k][j] : fr[k];
+                }
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    B b = q[i][0];
+#pragma unroll
+                    for (int j = 1; j < VW; ++j) b = jr == j ? q[i][j] : b;
+                    hr[i] = St::off_b(b, i);
+                }
+                const bool mv = (flw >> (8 * jr)) & ONSITE_MOVING;
+                onsite_rebuild<FM != FORCE_NONE>(hr, Ur, mv ? a.uw[0] : 0.0f, mv ? a.uw[1] : 0.0f,
+                                                 mv ? a.uw[2] : 0.0f, fr[0], fr[1], fr[2]);
+            }
+        }
         typename Vec<float, VW>::t mr, mx, my, mz;
 #pragma unroll
         for (int j = 0; j < VW; ++j) {
@@ -250,10 +284,15 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
                 h[i] = St::off_b(q[i][j], i);
                 if (i > 0 && ((mm[j] >> i) & 1u)) h[i] = h[i] + a.mw[i];
             }
-            if (ONSITE && os[j]) {
-                const bool mv = (flw >> (8 * j)) & ONSITE_MOVING;
-                onsite_rebuild<FM != FORCE_NONE>(h, os[j], mv ? a.uw[0] : 0.0f, mv ? a.uw[1] : 0.0f,
-                                                 mv ? a.uw[2] : 0.0f, F[0][j], F[1][j], F[2][j]);
+            if (ONSITE) {
+                if (jr == j) {
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) h[i] = hr[i];
+                } else if (os[j]) {
+                    const bool mv = (flw >> (8 * j)) & ONSITE_MOVING;
+                    onsite_rebuild<FM != FORCE_NONE>(h, os[j], mv ? a.uw[0] : 0.0f, mv ? a.uw[1] : 0.0f,
+                                                     mv ? a.uw[2] : 0.0f, F[0][j], F[1][j], F[2][j]);
+                }
             }
             const Macro m = bgk_collide<FM != FORCE_NONE>(h, a.omega, a.cF, F[0][j], F[1][j], F[2][j]);
             const bool sol = (solid >> (8 * j)) & 1u;
