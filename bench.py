@@ -171,6 +171,50 @@ def adjoint_rate(torch, n, T, K, tau):
     return N * T / dt / 1e6, gb
 
 
+def config_rates(torch, steps):
+    """Throughput of the other workload configurations: the 32^3 Taylor-Green
+    box (cache-resident, so no roofline), the 128x128x256 sphere duct in the
+    three storages (all points and fluid points only) and the 512^3 cavity in
+    FP32 two-array and FP16-offset in-place form."""
+    import workloads as W
+    from paper_1309_1983_amd import Lattice
+    out = {}
+    lat = Lattice(32, 32, 32, 0.8)
+    u0 = torch.from_numpy(W.taylor_green_velocity(32, 32, 32, 0.05).astype(np.float32))
+    lat.init_equilibrium(None, u0)
+    lat.step(20)
+    m = time_steps(lat, max(steps, 1000), torch)
+    lat.close()
+    out["tgv32_f32_ab"] = {"mlups": round(32 ** 3 / m / 1e3, 1), "ms_per_step": round(m, 5),
+                           "note": "5 MB state, cache-resident and launch-bound: no roofline"}
+    flags = W.sphere_duct_flags(128, 128, 256, seed=20130909, solid_fraction=0.10)
+    N = flags.size
+    nfl = int(np.count_nonzero(flags == 0))
+    for storage in ("f32", "f16", "bf16"):
+        lat = Lattice(128, 128, 256, 0.7, flags=flags, storage=storage)
+        lat.set_force((0.0, 0.0, 1e-6))
+        lat.step(20)
+        m = time_steps(lat, steps, torch)
+        lat.close()
+        bpp = BYTES_PER_POINT[storage]
+        out[f"spheres128x128x256_{storage}_ab"] = {
+            "mlups": round(N / m / 1e3, 1), "fluid_mlups": round(nfl / m / 1e3, 1),
+            "ms_per_step": round(m, 5), "gbs": round(bpp * N / m / 1e6, 1),
+            "frac": round(bpp * N / m / 1e6 / HBM_PEAK_GBS, 4), "fluid_fraction": round(nfl / N, 4)}
+    for storage, pattern in (("f32", "ab"), ("f16", "aa")):
+        lat = cavity_lattice(512, storage, pattern, 0.55, 0.05)
+        lat.step(4)
+        m = time_steps(lat, max(100, steps // 5), torch)
+        lat.close()
+        torch.cuda.empty_cache()
+        bpp = BYTES_PER_POINT[storage]
+        N = 512 ** 3
+        out[f"cavity512_{storage}_{pattern}"] = {
+            "mlups": round(N / m / 1e3, 1), "ms_per_step": round(m, 5), "gbs": round(bpp * N / m / 1e6, 1),
+            "frac": round(bpp * N / m / 1e6 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def _time_ms(torch, fn, reps):
     fn()
     torch.cuda.synchronize()
@@ -312,14 +356,25 @@ def main():
     workload = f"cavity{n}"
     log(f"device {torch.cuda.get_device_name(0)}; workload {workload}")
 
+    sweep = None
     if args.sweep:
-        for bx, by in [(64, 1), (128, 1), (256, 1), (64, 4), (128, 2), (256, 2), (256, 4), (32, 8)]:
-            lat = cavity_lattice(n, "f32", "ab", tau, lid, block=(bx, by))
+        # work-group shapes (Section 6 sweeps 64..1024 threads per block): the
+        # four-point kernel (up to 256 work-items = 1024 points per group) and
+        # the one-point kernel (up to 1024 work-items)
+        sweep = []
+        shapes = [(4, bx, by) for bx, by in [(16, 1), (32, 1), (64, 1), (128, 1), (256, 1), (64, 2),
+                                             (64, 4), (128, 2), (32, 8)]]
+        shapes += [(1, bx, by) for bx, by in [(64, 1), (128, 1), (256, 1), (512, 1), (1024, 1), (256, 4)]]
+        for cpl, bx, by in shapes:
+            lat = cavity_lattice(n, "f32", "ab", tau, lid, block=(bx, by), cells_per_lane=cpl)
             lat.step(args.warmup)
             ms = time_steps(lat, max(200, args.steps // 2), torch)
             lat.close()
-            log(f"sweep block {bx}x{by}: {ms:.4f} ms/step, {N / ms / 1e3:.0f} MLUPS, "
-                f"{BYTES_PER_POINT['f32'] * N / ms / 1e6:.0f} GB/s")
+            sweep.append({"points_per_work_item": cpl, "block": [bx, by], "points_per_group": cpl * bx * by,
+                          "ms_per_step": round(ms, 5), "mlups": round(N / ms / 1e3, 1),
+                          "gbs": round(BYTES_PER_POINT["f32"] * N / ms / 1e6, 1)})
+            log(f"sweep {cpl} point(s) per work-item, block {bx}x{by}: {ms:.4f} ms/step, "
+                f"{N / ms / 1e3:.0f} MLUPS, {BYTES_PER_POINT['f32'] * N / ms / 1e6:.0f} GB/s")
 
     # ---- headline: FP32 two-array step ----
     lat = cavity_lattice(n, "f32", "ab", tau, lid, block=args.block)
@@ -350,6 +405,8 @@ def main():
     }
     log(f"FP32 AB: {ms:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
+    if sweep is not None:
+        line["sweep"] = sweep
 
     if not args.no_extra:
         extra = {}
@@ -414,6 +471,10 @@ def main():
             log(f"adjoint: {ar:.0f} MLUPS (reverse sweep incl. recompute), {gb:.0f} GB on device")
         except Exception as e:  # noqa: BLE001
             extra["adjoint"] = {"error": str(e)}
+        log("other workload configurations")
+        extra["configs"] = config_rates(torch, args.steps)
+        for k, v in extra["configs"].items():
+            log(f"{k}: {v}")
         if args.timing_steps > 0:
             log(f"per-step timing log over {args.timing_steps} steps")
             extra["step_time"] = step_time_distribution(torch, n, args.timing_steps, tau, lid)
