@@ -247,9 +247,12 @@ struct FlagBytes<4> {
 // the state is gathered from x - e_i and the adjoint from x + e_i with the
 // 16-byte shifted accesses of the forward vector kernel (gather_vec); each
 // point then runs the same adj_cell arithmetic as the one-point kernel, so
-// b and dL/dF agree with it bit for bit.
+// b and dL/dF agree with it bit for bit. The launch bound asks for three
+// waves per SIMD: for two points per work-item that is 168 VGPRs with 24
+// bytes of spill per work-item instead of 174 VGPRs at two waves, and the
+// reverse sweep measured 11% faster (256^3 duct on MI355X).
 template <int FM, bool DIRECT, int VW>
-__global__ __launch_bounds__(256) void k_adj_stepv(const float* __restrict__ s,
+__global__ __launch_bounds__(256, 3) void k_adj_stepv(const float* __restrict__ s,
                                                    const float* __restrict__ bin,
                                                    float* __restrict__ bout, float* __restrict__ gF,
                                                    double* __restrict__ taupart,
