@@ -394,10 +394,12 @@ int orc_run(int nx, int ny, int nz, const uint8_t* flags, double tau, const doub
     double* tmp = (double*)malloc(sizeof(double) * Q * N);
     if (!tmp) return -2;
     int rc = 0;
+    double *a = s, *b = tmp;   /* the two copies of Section 4.1, swapped every step */
     for (int t = 0; t < nsteps && rc == 0; ++t) {
-        rc = orc_step(nx, ny, nz, flags, tau, uw, force_field, force_uniform, collide, s, tmp);
-        memcpy(s, tmp, sizeof(double) * Q * N);
+        rc = orc_step(nx, ny, nz, flags, tau, uw, force_field, force_uniform, collide, a, b);
+        double* c = a; a = b; b = c;
     }
+    if (a != s) memcpy(s, a, sizeof(double) * Q * N);
     free(tmp);
     return rc;
 }

@@ -211,3 +211,47 @@ def test_adjoint_config_64cube_vs_oracle_and_fd():
     lat.close()
     print(f"grad_tau adjoint {gt:.6e}, GPU central difference {fd:.6e}")
     assert gt == pytest.approx(fd, rel=0.05)
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_256cube_checkpoint_invariance_and_fd():
+    """The adjoint at the benchmarked size: 256^3 duct with a per-point force,
+    tau 0.7, T = 200. Checkpoints every 50 and every 40 steps give bitwise
+    equal gradients, and dL/dtau agrees with a GPU central difference."""
+    from paper_1309_1983_amd import Lattice
+    n, tau, T = 256, 0.7, 200
+    flags = W.duct_flags(n, n, n)
+    N = flags.size
+    fl = torch.from_numpy(flags == 0).cuda()
+    F = torch.from_numpy(W.random_force_field(N, 1, 1e-5).astype(np.float32)).cuda()
+    target = torch.from_numpy(W.random_velocity(N, 2, 1e-5).astype(np.float32)).cuda()
+    lat = Lattice(n, n, n, tau, flags=flags)
+    lat.set_force(F)
+    s0 = lat.populations()
+
+    def loss_and_grad(K):
+        lat.set_populations(s0)
+        lat.forward_checkpointed(T, K)
+        _, u = lat.macros()
+        d = (u - target)[:, fl]
+        loss = float((d.double() ** 2).sum() / fl.sum())
+        g = torch.zeros(3, N, device="cuda")
+        g[:, fl] = 2 * d / fl.sum()
+        gF, gt = lat.adjoint(g)
+        return loss, gF, gt
+
+    loss, gF50, gt50 = loss_and_grad(50)
+    _, gF40, gt40 = loss_and_grad(40)
+    assert torch.equal(gF50, gF40) and gt50 == gt40
+
+    def loss_at(t):
+        lat.set_tau(t)
+        lat.set_populations(s0)
+        lat.step(T)
+        _, u = lat.macros()
+        return float((((u - target)[:, fl]).double() ** 2).sum() / fl.sum())
+    h = 1e-2 * tau
+    fd = (loss_at(tau + h) - loss_at(tau - h)) / (2 * h)
+    lat.close()
+    print(f"256^3: loss {loss:.6e}, dL/dtau adjoint {gt50:.6e}, GPU central difference {fd:.6e}")
+    assert gt50 == pytest.approx(fd, rel=0.05)

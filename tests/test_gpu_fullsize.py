@@ -10,7 +10,9 @@ benchmark times (default work-group shape).
   (FP32), mass is conserved over 500 steps, and the FP16-offset AA run is
   reported against the FP32 run;
 - 128 x 128 x 256 sphere duct with body force: full-domain FP32 parity after
-  100 steps (<= 1e-5), and the FP16/BF16 offset error against the oracle.
+  100 steps (<= 1e-5), and the FP16/BF16 offset error against the oracle;
+  after 2000 steps (the workload's length) the error of all three storages
+  against the oracle is reported (the FP32 drift is bounded).
 """
 import numpy as np
 import pytest
@@ -167,3 +169,34 @@ def test_sphere_duct_full_size_vs_oracle(storage):
         # 16-bit offsets: reported; bounded by a few units of the format's
         # resolution relative to the offsets' size
         assert err <= (2e-3 if storage == "f16" else 2e-2)
+
+
+@pytest.mark.timeout(900)
+def test_sphere_duct_2000_steps_error_report():
+    """The sphere-duct workload over its full 2000 steps from rest: velocity
+    and population error of FP32, FP16-offset and BF16-offset storage
+    against the FP64 oracle (reported; FP32 bounded)."""
+    from paper_1309_1983_amd import Lattice
+    nx, ny, nz, tau, steps = 128, 128, 256, 0.7, 2000
+    flags = W.sphere_duct_flags(nx, ny, nz, seed=20130909, solid_fraction=0.10)
+    N = flags.size
+    fl = flags == 0
+    force = (0.0, 0.0, 1e-6)
+    olat = oracle_lattice((nx, ny, nz), tau, flags=flags, force=force)
+    ref = olat.run(oracle.init_equilibrium(N), steps)
+    _, uo = olat.macros(ref)
+    umax = np.abs(uo[:, fl]).max()
+    errs = {}
+    for storage in ("f32", "f16", "bf16"):
+        lat = Lattice(nx, ny, nz, tau, flags=flags, storage=storage)
+        lat.set_force(force)
+        lat.step(steps)
+        got = lat.populations().cpu().numpy().astype(np.float64)
+        _, ug = lat.macros()
+        lat.close()
+        du = ug.cpu().numpy()[:, fl] - uo[:, fl]
+        errs[storage] = (fluid_rel_err(got, ref, flags), np.abs(du).max() / umax,
+                         np.sqrt((du ** 2).mean()) / umax)
+        print(f"spheres {storage}, {steps} steps from rest: max rel |df| {errs[storage][0]:.3e}, "
+              f"max |du|/max|u| {errs[storage][1]:.3e}, RMS {errs[storage][2]:.3e} (max|u| {umax:.3e})")
+    assert errs["f32"][0] <= 1e-5 and errs["f32"][1] <= 1e-3
