@@ -485,6 +485,11 @@ __device__ __forceinline__ void onsite_rebuild(float h[Q], uint32_t U, float ux,
 }
 
 // Returns the in-step macroscopic values (rho, u = (m + F/2)/rho).
+// Opposite directions i, opp(i) share e.u up to sign, so the equilibrium and
+// the Guo source are split into a part even in e and a part odd in e and
+// evaluated once per pair:
+//   f^eq_i - w_i = w_i (A + 4.5 rho (e.u)^2) +- 3 w_i rho (e.u)
+//   G_i          = w_i (9 (e.u)(e.F) - 3 u.F) +- 3 w_i (e.F)
 template <bool FORCE>
 __device__ __forceinline__ Macro bgk_collide(float h[Q], float omega, float cF, float Fx, float Fy,
                                              float Fz)
@@ -493,11 +498,27 @@ __device__ __forceinline__ Macro bgk_collide(float h[Q], float omega, float cF, 
     const float A = eq_A(m);
     float uF = 0.0f;
     if (FORCE) uF = fmaf(m.ux, Fx, fmaf(m.uy, Fy, m.uz * Fz));
+    h[0] = fmaf(omega, weight(0) * A - h[0], h[0]);
+    if (FORCE) h[0] = fmaf(cF, weight(0) * (-3.0f * uF), h[0]);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        float out = fmaf(omega, heq(i, m, A) - h[i], h[i]);
-        if (FORCE) out = fmaf(cF, guo(i, m, Fx, Fy, Fz, uF), out);
-        h[i] = out;
+    for (int i = 1; i < Q; i += 2) {
+        const int k = i + 1;                        // OPP[i]
+        const float w = weight(i);
+        const float eu = edot(i, m.ux, m.uy, m.uz);
+        const float reu = m.rho * eu;
+        const float even = w * fmaf(4.5f * reu, eu, A);
+        const float odd = (3.0f * w) * reu;
+        float oi = fmaf(omega, (even + odd) - h[i], h[i]);
+        float ok = fmaf(omega, (even - odd) - h[k], h[k]);
+        if (FORCE) {
+            const float eF = edot(i, Fx, Fy, Fz);
+            const float geven = w * fmaf(9.0f * eu, eF, -3.0f * uF);
+            const float godd = (3.0f * w) * eF;
+            oi = fmaf(cF, geven + godd, oi);
+            ok = fmaf(cF, geven - godd, ok);
+        }
+        h[i] = oi;
+        h[k] = ok;
     }
     return m;
 }
