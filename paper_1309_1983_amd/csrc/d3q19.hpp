@@ -191,9 +191,13 @@ __device__ __forceinline__ void load_words(const uint32_t* __restrict__ base, ui
 // Directions with e_x != 0 are single accesses shifted by one element; the
 // row ends are clamped into the row and the wrapped element is loaded on its
 // own, only when the end point needs it (end0/endL: first/last point fluid).
-// Opposite directions (i, i+1), i odd, sit in adjacent planes, so one load
-// with a per-work-item plane choice serves whichever bounced value a
-// work-item needs.
+// Bounced values: when more than two work-items of the wave have near-wall
+// points (porous geometry, wall rows, narrow ducts), each loads all 18 of its
+// own moving planes at once, without waiting for the neighbour mask (10%
+// faster on the sphere duct, 5% on the 128-wide duct); when only the two row
+// ends of a row do (the cavity), each loads just the planes its mask asks
+// for (3.5% faster for the 16-bit cavity). The choice is wave-uniform; every
+// work-item of the wave calls this function.
 // ---------------------------------------------------------------------------
 template <int SIGN, int VW, class B>
 __device__ __forceinline__ void gather_vec(const B* __restrict__ src, const Dims& d, uint32_t z,
@@ -253,7 +257,30 @@ __device__ __forceinline__ void gather_vec(const B* __restrict__ src, const Dims
             q[i] = wr ? s : v;
         }
     }
-    if (near_wall) {
+    // wave-wide count of work-items with near-wall points (every work-item
+    // of the wave that reached the gather takes part)
+    const int nw_lanes = __builtin_popcountll(__builtin_amdgcn_ballot_w64(near_wall));
+    if (near_wall && nw_lanes > 2) {
+        // several near-wall work-items: load all 18 own planes at once
+        const B* base = plane(src, d, 0, z);
+        Vt loc[Q];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) loc[i] = ldv<VW>(base, (uint32_t)i * d.nxy + o0);
+        uint32_t sm[VW];
+        load_words<VW>(smask, c0, sm);
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int bit = SIGN > 0 ? i : OPP[i];
+            Vt v = q[i];
+#pragma unroll
+            for (int j = 0; j < VW; ++j)
+                if ((sm[j] >> bit) & 1u) v[j] = loc[OPP[i]][j];
+            q[i] = v;
+        }
+    } else if (near_wall) {
+        // few: load only the planes the neighbour mask asks for; opposite
+        // directions (i, i+1), i odd, sit in adjacent planes, so one load
+        // with a per-work-item plane choice serves either bounced value
         uint32_t sm[VW];
         load_words<VW>(smask, c0, sm);
         uint32_t any = 0;
