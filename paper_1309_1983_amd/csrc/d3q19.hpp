@@ -122,6 +122,17 @@ __device__ __forceinline__ void stv(B* base, uint32_t idx, typename Vec<B, VW>::
 {
     *reinterpret_cast<typename Vec<B, VW>::t*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(B)) = v;
 }
+// Non-temporal (streaming) vector store, for whole-wave store streams that
+// the same launch does not read back: the populations a step writes and the
+// adjoint's outputs. On MI355X it made the 256^3 two-array step 6% faster
+// and the adjoint reverse step 7% faster; the narrow stores of the one-point
+// kernels and the gathers' loads measured slower with the hint.
+template <int VW, class B>
+__device__ __forceinline__ void stv_nt(B* base, uint32_t idx, typename Vec<B, VW>::t v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<typename Vec<B, VW>::t*>(reinterpret_cast<char*>(base) +
+                                                                              idx * (uint32_t)sizeof(B)));
+}
 template <class B>
 __device__ __forceinline__ typename V4<B>::t ld4(const B* base, uint32_t idx) { return ldv<4>(base, idx); }
 

@@ -335,9 +335,9 @@ __global__ __launch_bounds__(256, 3) void k_adj_stepv(const float* __restrict__ 
             }
         }
 #pragma unroll
-        for (int i = 0; i < Q; ++i) stv<VW>(plane(bout, d, i, z), o0, aq[i]);
+        for (int i = 0; i < Q; ++i) stv_nt<VW>(plane(bout, d, i, z), o0, aq[i]);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) stv<VW>(gF + k * N, c0, gv[k]);
+        for (int k = 0; k < 3; ++k) stv_nt<VW>(gF + k * N, c0, gv[k]);
     }
 
     block_tau_sum(tsum, taupart);

@@ -86,7 +86,7 @@ __device__ __forceinline__ void store_rest(P* fp, const Dims& d, uint32_t z, uin
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const typename Vec<typename St::bits_t, VW>::t r = St::enc_b(0.0f, i);
-        stv<VW>(plane(f, d, i, z), o0, r);
+        stv_nt<VW>(plane(f, d, i, z), o0, r);
     }
 }
 
@@ -207,9 +207,9 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
     if (solid == ONES) {
         if (MACROS) {
             const typename Vec<float, VW>::t zero = 0.0f;
-            stv<VW>(rho_out, c0, zero);
+            stv_nt<VW>(rho_out, c0, zero);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) stv<VW>(u_out + k * (size_t)d.N, c0, zero);
+            for (int k = 0; k < 3; ++k) stv_nt<VW>(u_out + k * (size_t)d.N, c0, zero);
         }
         if (wave_fluid) store_rest<St, VW>(dst, d, z, o0);
         return;
@@ -327,14 +327,14 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
             }
         }
         if (MACROS) {
-            stv<VW>(rho_out, c0, mr);
-            stv<VW>(u_out, c0, mx);
-            stv<VW>(u_out + (size_t)d.N, c0, my);
-            stv<VW>(u_out + 2 * (size_t)d.N, c0, mz);
+            stv_nt<VW>(rho_out, c0, mr);
+            stv_nt<VW>(u_out, c0, mx);
+            stv_nt<VW>(u_out + (size_t)d.N, c0, my);
+            stv_nt<VW>(u_out + 2 * (size_t)d.N, c0, mz);
         }
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) stv<VW>(plane(dst, d, i, z), o0, q[i]);
+    for (int i = 0; i < Q; ++i) stv_nt<VW>(plane(dst, d, i, z), o0, q[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -581,12 +581,15 @@ __global__ __launch_bounds__(1024) void k_mark_near_wall(const uint8_t* __restri
     mmask[c] = mm;
 }
 
+// Bandwidth probe: one 16-byte load and one 16-byte store per work-item, the
+// store non-temporal like the vector step's stores.
 __global__ __launch_bounds__(256) void k_copy(const float* __restrict__ src, float* __restrict__ dst,
                                               size_t n)
 {
     const size_t k = 4 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
     if (k + 4 <= n) {
-        *reinterpret_cast<typename V4<float>::t*>(dst + k) = *reinterpret_cast<const typename V4<float>::t*>(src + k);
+        __builtin_nontemporal_store(*reinterpret_cast<const typename V4<float>::t*>(src + k),
+                                    reinterpret_cast<typename V4<float>::t*>(dst + k));
     } else {
         for (size_t e = k; e < n; ++e) dst[e] = src[e];
     }
