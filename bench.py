@@ -272,28 +272,50 @@ def access_study(torch, n=256):
     return out
 
 
-def cpu_baseline(n, tau, lid, budget_s=12.0):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _oracle_steps(lat, s, budget_s, max_steps):
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        s = lat.step(s)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= max_steps:
+            break
+    return steps, time.perf_counter() - t0
+
+
+def cpu_baseline(n, tau, lid, budget_s=12.0, single_budget_s=8.0):
     """The FP64 oracle on the host: whole 256^3 cavity steps, as many as fit
-    the time budget (at least one)."""
+    the time budget (at least one), on all the threads OpenMP takes, then on
+    one thread (reported beside it as context)."""
     import oracle
     import workloads as W
     flags = W.cavity_flags(n, n, n)
     N = flags.size
     lat = oracle.Lattice(n, n, n, float(np.float32(tau)), flags=flags, uw=(float(np.float32(lid)), 0, 0))
     s = oracle.init_equilibrium(N)
-    out = np.empty_like(s)
-    steps, t0 = 0, time.perf_counter()
-    while True:
-        out = lat.step(s)
-        s, out = out, s
-        steps += 1
-        if time.perf_counter() - t0 > budget_s or steps >= 50:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": N * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
+    threads = oracle.num_threads()
+    steps, dt = _oracle_steps(lat, s, budget_s, 50)
+    oracle.set_num_threads(1)
+    try:
+        steps1, dt1 = _oracle_steps(lat, s, single_budget_s, 50)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": N * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "sample": f"{steps} FP64 steps of the full {n}^3 cavity ({dt:.1f} s, "
-                      f"{platform.processor() or platform.machine()}, nproc={os.cpu_count()})"}
+            "sample": f"{steps} FP64 steps of the full {n}^3 cavity ({dt:.1f} s, {_cpu_model()}, "
+                      f"nproc={os.cpu_count()})",
+            "one_thread": {"value": N * steps1 / dt1 / 1e6, "unit": "MLUPS",
+                           "sample": f"{steps1} FP64 steps of the same cavity on 1 thread ({dt1:.1f} s)"}}
 
 
 def main():

@@ -67,6 +67,7 @@ def lib():
                                   dp, dp, dp, ctypes.c_int, dp, dp, dp]
         L.orc_adjoint.restype = ctypes.c_int
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -216,3 +217,8 @@ def quantize(f, fmt):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later oracle calls (OpenMP builds only)."""
+    lib().orc_set_num_threads(int(n))
