@@ -17,6 +17,9 @@ struct StepArgs {
     float Fx, Fy, Fz;           // uniform force (FORCE_UNIFORM)
     float mw[d3q19::Q];         // 6 w_i (e_i . u_wall), rho_wall = 1
     float uw[3];                // wall velocity (velocity of moving on-site nodes)
+    uint32_t gx;                // vector AB step: > 0 = its grid is one-dimensional in x over
+                                // the gx * ny point groups of a z-plane (gx = nx / vw groups
+                                // per row, x fastest); 0 = two-dimensional (x groups, y)
 };
 
 struct Launch {

@@ -178,7 +178,7 @@ struct FlagWord<8> {
     static constexpr uint64_t ones = 0x0101010101010101ull;
 };
 
-template <class St, int FM, bool COLLIDE, int VW, bool MACROS, bool ONSITE>
+template <class St, int FM, bool COLLIDE, int VW, bool MACROS, bool ONSITE, bool FLAT>
 __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __restrict__ src,
                                                   typename St::bits_t* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
@@ -192,8 +192,19 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
     using FW = typename FlagWord<VW>::t;
     constexpr FW ONES = FlagWord<VW>::ones;
     const Dims& d = a.d;
-    const int x0 = VW * (int)(blockIdx.x * blockDim.x + threadIdx.x);
-    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    // FLAT: rows whose group count is not a multiple of the wave width run
+    // on a one-dimensional grid over the plane (a.gx groups per row), so
+    // that every wave is full.
+    const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+    int x0, y;
+    if (FLAT) {
+        const uint32_t gy = gid / a.gx;
+        x0 = VW * (int)(gid - gy * a.gx);
+        y = (int)gy;
+    } else {
+        x0 = VW * (int)gid;
+        y = blockIdx.y * blockDim.y + threadIdx.y;
+    }
     const uint32_t z = blockIdx.z;
     if (x0 >= d.nx || y >= d.ny) return;
     const uint32_t nx = (uint32_t)d.nx;
@@ -659,21 +670,30 @@ hipError_t launch_step(int storage, int pattern, int parity, bool collide, int f
                : step_os<false>(storage, pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
 }
 
-template <class St, int FM, int VW, bool ONSITE>
-static hipError_t stepv_fm(bool collide, void* a, void* b, const uint8_t* flags, const uint32_t* sm,
-                           const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L,
-                           float* rho, float* u)
+template <class St, int FM, int VW, bool ONSITE, bool FLAT>
+static hipError_t stepv_grid(bool collide, void* a, void* b, const uint8_t* flags, const uint32_t* sm,
+                             const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L,
+                             float* rho, float* u)
 {
     using B = typename St::bits_t;
     const B* A = static_cast<const B*>(a);
     B* Bp = static_cast<B*>(b);
     if (collide && rho)
-        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, true, ONSITE>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, true, ONSITE, FLAT>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     else if (collide)
-        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, false, ONSITE>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, false, ONSITE, FLAT>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     else
-        hipLaunchKernelGGL((k_step_abv<St, FORCE_NONE, false, VW, false, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        hipLaunchKernelGGL((k_step_abv<St, FORCE_NONE, false, VW, false, false, FLAT>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     return hipGetLastError();
+}
+
+template <class St, int FM, int VW, bool ONSITE>
+static hipError_t stepv_fm(bool collide, void* a, void* b, const uint8_t* flags, const uint32_t* sm,
+                           const uint32_t* mm, const float* ff, const StepArgs& args, const Launch& L,
+                           float* rho, float* u)
+{
+    return args.gx ? stepv_grid<St, FM, VW, ONSITE, true>(collide, a, b, flags, sm, mm, ff, args, L, rho, u)
+                   : stepv_grid<St, FM, VW, ONSITE, false>(collide, a, b, flags, sm, mm, ff, args, L, rho, u);
 }
 
 template <class St, int VW, bool ONSITE>

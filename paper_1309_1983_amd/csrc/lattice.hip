@@ -69,6 +69,7 @@ struct lbm_lattice {
     int cpl = 1;                   // points per work-item of the AB step (1 or the vector width)
     bool vec_ok = true;            // vector kernels allowed (cells_per_lane != 1)
     int bx4 = 64, by4 = 1;         // work-group of the vector kernel
+    bool flat = false;             // vector AB step on a one-dimensional grid per plane
     bool onsite = false;           // has on-site velocity nodes (flags 3, 4)
 
     bool sticky = false;
@@ -154,6 +155,7 @@ lbmk::StepArgs step_args(const lbm_lattice* L)
         a.mw[i] = (float)(6.0 * (double)d3q19::weight(i) * eu);
     }
     for (int k = 0; k < 3; ++k) a.uw[k] = L->uw[k];
+    a.gx = L->flat ? (uint32_t)(L->nx / L->cpl) : 0u;
     return a;
 }
 
@@ -162,6 +164,14 @@ lbmk::Launch launch_of(const lbm_lattice* L) { return lbmk::make_launch(L->dims,
 // Only valid when the lattice uses the vector kernel (cpl > 1).
 lbmk::Launch launch4_of(const lbm_lattice* L)
 {
+    if (L->flat) {
+        const unsigned long long groups = (unsigned long long)(L->nx / L->cpl) * (unsigned long long)L->ny;
+        lbmk::Launch la;
+        la.block = dim3(64, 1, 1);
+        la.grid = dim3((unsigned)((groups + 63) / 64), 1, (unsigned)L->nz);
+        la.stream = L->stream;
+        return la;
+    }
     d3q19::Dims q = L->dims;
     q.nx = L->nx / L->cpl;   // the grid counts groups of cpl points along x
     return lbmk::make_launch(q, L->bx4, L->by4, L->stream);
@@ -278,12 +288,17 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
     const bool wide = opt.storage != LBM_STORAGE_F32 && nx % 8 == 0 && nx >= 256;
     const int vw = opt.cells_per_lane > 1 ? opt.cells_per_lane : (wide ? 8 : 4);
     int cpl = 1, bx4 = 0, by4 = 0;
+    bool flat = false;
     if (opt.pattern == LBM_PATTERN_AB && nx % vw == 0 && opt.cells_per_lane != 1) {
         if (opt.block_x == 0 && opt.block_y == 0) {
             // one wave per work-group along x (a whole 256-point row when
-            // nx = 256 and vw = 4): the fastest shape measured at 256^3 on MI355X
+            // nx = 256 and vw = 4): the fastest shape measured at 256^3 on MI355X.
+            // Rows of more than 64 groups that are not a multiple of 64 (a
+            // 260-point row: 65 groups) take a one-dimensional grid over the
+            // plane instead, which keeps every wave full.
             bx4 = std::min(nx / vw, 64);
             by4 = std::max(1, 64 / bx4);
+            flat = nx / vw > 64 && (nx / vw) % 64 != 0;
             cpl = vw;
         } else if (bx * by <= 256) {
             bx4 = bx; by4 = by;
@@ -326,7 +341,7 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
     L->cpl = cpl;
     L->vec_ok = opt.cells_per_lane != 1;
     L->onsite = onsite;
-    if (cpl > 1) { L->bx4 = bx4; L->by4 = by4; }
+    if (cpl > 1) { L->bx4 = bx4; L->by4 = by4; L->flat = flat; }
 
     lbm_status st = LBM_OK;
     const size_t fbytes = (size_t)Q * L->N * storage_bytes(L->storage);

@@ -51,3 +51,28 @@ def test_resolution_differences_recover_the_order_of_a_known_error():
     diffs, orders = cavity.resolution_differences(res)
     assert diffs[0] > diffs[1] > 0
     assert orders[0] == pytest.approx(2.0, abs=1e-9)
+
+
+def test_common_nodes_of_a_three_to_two_refinement():
+    ia, ib = cavity.common_nodes(8, 12)
+    np.testing.assert_array_equal(ia, [0, 2, 4, 6, 8])
+    np.testing.assert_array_equal(ib, [0, 3, 6, 9, 12])
+    np.testing.assert_allclose(ia / 8, ib / 12, rtol=0, atol=0)
+    ia, ib = cavity.common_nodes(16, 32)
+    np.testing.assert_array_equal(ia, np.arange(17))
+    np.testing.assert_array_equal(ib, 2 * np.arange(17))
+
+
+def test_resolution_differences_at_a_three_to_two_refinement():
+    # exact + C h^2 on grids of side 8, 12, 18: the differences at the shared
+    # positions are C (h_a^2 - h_b^2) cos(s) and give order 2 at ratio 3/2
+    exact = lambda s: np.sin(np.pi * s)
+    res = []
+    for L in (8, 12, 18):
+        s = np.arange(L + 1) / L
+        res.append(_result(L, exact(s), exact(s) + 0.3 * (1.0 / L) ** 2 * np.cos(s)))
+    diffs, orders = cavity.resolution_differences(res)
+    assert diffs[0] == pytest.approx(0.3 * (1 / 64 - 1 / 144), rel=1e-12)
+    assert orders[0] == pytest.approx(2.0, abs=1e-9)
+    with pytest.raises(ValueError):
+        cavity.resolution_differences([res[0], res[0]])

@@ -68,6 +68,8 @@ CASES = {
     "ragged_one_point": ((13, 11, 10), 0.7, (0.05, 0.01, -0.02), None, 1e-4),
     "vector": ((16, 12, 10), 0.65, (0.08, 0.0, 0.0), (1e-5, -2e-5, 5e-6), None),
     "vector_field": ((24, 9, 7), 0.9, (0.03, -0.02, 0.04), None, 1e-4),
+    # 65 four-point groups per row: the vector step's one-dimensional grid
+    "flat_rows": ((260, 7, 6), 0.7, (0.05, 0.0, 0.01), (2e-5, 0.0, 0.0), None),
 }
 
 

@@ -238,6 +238,8 @@ FOUR_CELL_CASES = [
     ((256, 3, 2), 0.3, 0.1, (0, 0, 1e-5), False),
     ((8, 6, 5), 0.1, 0.05, None, True),         # one 8-point group per row
     ((40, 7, 3), 0.0, 0.0, None, True),         # periodic in x, five 8-point groups per row
+    ((260, 5, 3), 0.2, 0.05, None, True),       # 65 four-point groups per row: one-dimensional grid
+    ((520, 3, 2), 0.1, 0.05, (1e-5, 0, 0), False),   # 65 eight-point groups per row
 ]
 
 
