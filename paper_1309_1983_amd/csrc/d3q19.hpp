@@ -202,13 +202,17 @@ __device__ __forceinline__ void load_words(const uint32_t* __restrict__ base, ui
 // Directions with e_x != 0 are single accesses shifted by one element; the
 // row ends are clamped into the row and the wrapped element is loaded on its
 // own, only when the end point needs it (end0/endL: first/last point fluid).
-// Bounced values: when more than two work-items of the wave have near-wall
-// points (porous geometry, wall rows, narrow ducts), each loads all 18 of its
-// own moving planes at once, without waiting for the neighbour mask (10%
-// faster on the sphere duct, 5% on the 128-wide duct); when only the two row
-// ends of a row do (the cavity), each loads just the planes its mask asks
-// for (3.5% faster for the 16-bit cavity). The choice is wave-uniform; every
-// work-item of the wave calls this function.
+// Bounced values: a work-item with near-wall points loads its neighbour mask
+// before the gather's loads, then, after them, one plane per opposite pair
+// that the mask names, all without waiting in between (opposite directions
+// sit in adjacent planes, so one load with a per-work-item plane choice
+// serves either bounced value of a pair). With 16-bit storage and more than
+// four near-wall work-items in the wave (porous geometry) it loads all 18 of
+// its own planes at once instead, each load coalesced over the wave. Measured
+// on MI355X against loading all 18 planes whenever more than two work-items
+// are near a wall: FP32 cavity +0.3%, sphere duct +1.8%, 128-wide duct +2.9%,
+// adjoint +6%; 16-bit cavity +3-5%, duct +7%, sphere duct -1 to -3%. The
+// choice is wave-uniform; every work-item of the wave calls this function.
 // ---------------------------------------------------------------------------
 template <int SIGN, int VW, class B>
 __device__ __forceinline__ void gather_vec(const B* __restrict__ src, const Dims& d, uint32_t z,
@@ -224,6 +228,13 @@ __device__ __forceinline__ void gather_vec(const B* __restrict__ src, const Dims
     const bool wr = x0 + VW == nx;
     const uint32_t xm = wl ? x0 : x0 - 1;   // group start when reading x - 1
     const uint32_t xp = wr ? x0 : x0 + 1;   // group start when reading x + 1
+    // wave-wide count of work-items with near-wall points
+    const int nw_lanes = __builtin_popcountll(__builtin_amdgcn_ballot_w64(near_wall));
+    const bool all_planes = sizeof(B) == 2 && nw_lanes > 4;
+    uint32_t smw[VW];   // neighbour mask, loaded first unless all planes are loaded
+#pragma unroll
+    for (int j = 0; j < VW; ++j) smw[j] = 0u;
+    if (near_wall && !all_planes) load_words<VW>(smask, c0, smw);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = SIGN * EX[i], ey = SIGN * EY[i];
@@ -268,11 +279,7 @@ __device__ __forceinline__ void gather_vec(const B* __restrict__ src, const Dims
             q[i] = wr ? s : v;
         }
     }
-    // wave-wide count of work-items with near-wall points (every work-item
-    // of the wave that reached the gather takes part)
-    const int nw_lanes = __builtin_popcountll(__builtin_amdgcn_ballot_w64(near_wall));
-    if (near_wall && nw_lanes > 2) {
-        // several near-wall work-items: load all 18 own planes at once
+    if (near_wall && all_planes) {
         const B* base = plane(src, d, 0, z);
         Vt loc[Q];
 #pragma unroll
@@ -289,39 +296,48 @@ __device__ __forceinline__ void gather_vec(const B* __restrict__ src, const Dims
             q[i] = v;
         }
     } else if (near_wall) {
-        // few: load only the planes the neighbour mask asks for; opposite
-        // directions (i, i+1), i odd, sit in adjacent planes, so one load
-        // with a per-work-item plane choice serves either bounced value
-        uint32_t sm[VW];
-        load_words<VW>(smask, c0, sm);
+        // one load per opposite pair (i, i+1), i odd, that any point needs:
+        // direction i+1 at x when q[i]'s neighbour is solid, else direction i
         uint32_t any = 0;
 #pragma unroll
-        for (int j = 0; j < VW; ++j) any |= sm[j];
+        for (int j = 0; j < VW; ++j) any |= smw[j];
         const B* pair_base = plane(src, d, 0, z);
+        Vt bb[Q / 2];
 #pragma unroll
-        for (int i = 1; i < Q; i += 2) {
-            const int k = i + 1;                     // OPP[i] == k
-            const int bi = SIGN > 0 ? i : k;         // mask bit: is q[i]'s neighbour solid
-            const int bk = SIGN > 0 ? k : i;         // mask bit for q[k]
+        for (int p = 0; p < Q / 2; ++p) {
+            const int i = 2 * p + 1, k = i + 1;
+            const int bi = SIGN > 0 ? i : k;
+            const bool need_i = (any >> bi) & 1u;
+            const int bk = SIGN > 0 ? k : i;
+            const bool need_k = (any >> bk) & 1u;
+            if (need_i || need_k) bb[p] = ldv<VW>(pair_base, (need_i ? (uint32_t)k : (uint32_t)i) * d.nxy + o0);
+        }
+#pragma unroll
+        for (int p = 0; p < Q / 2; ++p) {
+            const int i = 2 * p + 1, k = i + 1;
+            const int bi = SIGN > 0 ? i : k;
+            const int bk = SIGN > 0 ? k : i;
             const bool need_i = (any >> bi) & 1u, need_k = (any >> bk) & 1u;
-            if (need_i || need_k) {
-                // bounced value of q[i] is direction k at x, of q[k] direction i
-                const uint32_t pl = need_i ? (uint32_t)k : (uint32_t)i;
-                const Vt bb = ldv<VW>(pair_base, pl * d.nxy + o0);
-                const int t = need_i ? bi : bk;
-                Vt v = need_i ? q[i] : q[k];
+            if (need_i) {
+                Vt v = q[i];
 #pragma unroll
                 for (int j = 0; j < VW; ++j)
-                    if ((sm[j] >> t) & 1u) v[j] = bb[j];
-                if (need_i) q[i] = v; else q[k] = v;
-                if (need_i && need_k) {
-                    const Vt b2 = ldv<VW>(pair_base, (uint32_t)i * d.nxy + o0);
-                    Vt w = q[k];
+                    if ((smw[j] >> bi) & 1u) v[j] = bb[p][j];
+                q[i] = v;
+            } else if (need_k) {
+                Vt v = q[k];
 #pragma unroll
-                    for (int j = 0; j < VW; ++j)
-                        if ((sm[j] >> bk) & 1u) w[j] = b2[j];
-                    q[k] = w;
-                }
+                for (int j = 0; j < VW; ++j)
+                    if ((smw[j] >> bk) & 1u) v[j] = bb[p][j];
+                q[k] = v;
+            }
+            if (need_i && need_k) {   // both of the pair bounce somewhere in the group (rare)
+                const Vt b2 = ldv<VW>(pair_base, (uint32_t)i * d.nxy + o0);
+                Vt w = q[k];
+#pragma unroll
+                for (int j = 0; j < VW; ++j)
+                    if ((smw[j] >> bk) & 1u) w[j] = b2[j];
+                q[k] = w;
             }
         }
     }
