@@ -174,8 +174,9 @@ def adjoint_rate(torch, n, T, K, tau):
 def config_rates(torch, steps):
     """Throughput of the other workload configurations: the 32^3 Taylor-Green
     box (cache-resident, so no roofline), the 128x128x256 sphere duct in the
-    three storages (all points and fluid points only) and the 512^3 cavity in
-    FP32 two-array and FP16-offset in-place form."""
+    three storages, two-array, and in FP32 and FP16 offsets in place (all
+    points and fluid points only), and the 512^3 cavity in FP32 two-array and
+    FP16-offset in-place form."""
     import workloads as W
     from paper_1309_1983_amd import Lattice
     out = {}
@@ -190,14 +191,14 @@ def config_rates(torch, steps):
     flags = W.sphere_duct_flags(128, 128, 256, seed=20130909, solid_fraction=0.10)
     N = flags.size
     nfl = int(np.count_nonzero(flags == 0))
-    for storage in ("f32", "f16", "bf16"):
-        lat = Lattice(128, 128, 256, 0.7, flags=flags, storage=storage)
+    for storage, pattern in (("f32", "ab"), ("f16", "ab"), ("bf16", "ab"), ("f32", "aa"), ("f16", "aa")):
+        lat = Lattice(128, 128, 256, 0.7, flags=flags, storage=storage, pattern=pattern)
         lat.set_force((0.0, 0.0, 1e-6))
         lat.step(20)
         m = time_steps(lat, steps, torch)
         lat.close()
         bpp = BYTES_PER_POINT[storage]
-        out[f"spheres128x128x256_{storage}_ab"] = {
+        out[f"spheres128x128x256_{storage}_{pattern}"] = {
             "mlups": round(N / m / 1e3, 1), "fluid_mlups": round(nfl / m / 1e3, 1),
             "ms_per_step": round(m, 5), "gbs": round(bpp * N / m / 1e6, 1),
             "frac": round(bpp * N / m / 1e6 / HBM_PEAK_GBS, 4), "fluid_fraction": round(nfl / N, 4)}

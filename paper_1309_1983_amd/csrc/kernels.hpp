@@ -34,9 +34,9 @@ Launch make_launch(const d3q19::Dims& d, int bx, int by, hipStream_t s);
 // AB only: rho/u non-null also stores the in-step rho [N] and u [3][N].
 // onsite: the lattice has on-site velocity nodes (rebuilt when collide).
 hipError_t launch_step(int storage, int pattern, int parity, bool collide, int force_mode,
-                       void* a, void* b, const uint8_t* flags, const float* ffield,
-                       const StepArgs& args, const Launch& L, float* rho = nullptr,
-                       float* u = nullptr, bool onsite = false);
+                       void* a, void* b, const uint8_t* flags, const uint32_t* smask,
+                       const uint32_t* mmask, const float* ffield, const StepArgs& args,
+                       const Launch& L, float* rho = nullptr, float* u = nullptr, bool onsite = false);
 
 // One AB step with vw consecutive x-points per work-item: vw = 4 (FP32,
 // 16-byte accesses; or 16-bit storage, 8-byte accesses) or vw = 8 (16-bit

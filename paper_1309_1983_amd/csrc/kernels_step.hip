@@ -101,6 +101,8 @@ template <class St, int FM, bool COLLIDE, bool MACROS, bool ONSITE>
 __global__ __launch_bounds__(1024) void k_step_ab(const typename St::raw_t* __restrict__ src,
                                                   typename St::raw_t* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
+                                                  const uint32_t* __restrict__ smask,
+                                                  const uint32_t* __restrict__ mmask,
                                                   const float* __restrict__ ff, StepArgs a,
                                                   float* __restrict__ rho_out, float* __restrict__ u_out)
 {
@@ -124,15 +126,11 @@ __global__ __launch_bounds__(1024) void k_step_ab(const typename St::raw_t* __re
 
     uint32_t mwmask = 0, solid = 0;
     if (fl & NEAR_WALL) {
+        solid = smask[c];
+        if (fl & NEAR_MOVING) mwmask = mmask[c];
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const uint8_t nf = flags[src_slab(i, z, zm, zp) * d.nxy + on[i]];
-            if (nf & TYPE_MASK) {
-                solid |= 1u << i;
-                raw[i] = ld(plane(src, d, OPP[i], z), o);
-                if (nf & MOVING) mwmask |= 1u << i;
-            }
-        }
+        for (int i = 1; i < Q; ++i)
+            if ((solid >> i) & 1u) raw[i] = ld(plane(src, d, OPP[i], z), o);
     }
 
     if (!COLLIDE) {
@@ -361,6 +359,8 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
 template <class St, int FM, bool COLLIDE, bool ONSITE>
 __global__ __launch_bounds__(1024) void k_step_aa0(typename St::raw_t* f,
                                                    const uint8_t* __restrict__ flags,
+                                                   const uint32_t* __restrict__ smask,
+                                                   const uint32_t* __restrict__ mmask,
                                                    const float* __restrict__ ff, StepArgs a)
 {
     using T = typename St::raw_t;
@@ -377,15 +377,11 @@ __global__ __launch_bounds__(1024) void k_step_aa0(typename St::raw_t* f,
 
     uint32_t solid = 0, mwmask = 0;
     if (fl & NEAR_WALL) {
+        solid = smask[c];
+        if (fl & NEAR_MOVING) mwmask = mmask[c];
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const uint8_t nf = flags[src_slab(i, z, zm, zp) * d.nxy + on[i]];
-            if (nf & TYPE_MASK) {
-                solid |= 1u << i;
-                raw[i] = ld(plane(f, d, OPP[i], z), o);
-                if (nf & MOVING) mwmask |= 1u << i;
-            }
-        }
+        for (int i = 1; i < Q; ++i)
+            if ((solid >> i) & 1u) raw[i] = ld(plane(f, d, OPP[i], z), o);
     }
 
     float h[Q];
@@ -404,6 +400,8 @@ __global__ __launch_bounds__(1024) void k_step_aa0(typename St::raw_t* f,
 template <class St, int FM, bool COLLIDE, bool ONSITE>
 __global__ __launch_bounds__(1024) void k_step_aa1(typename St::raw_t* f,
                                                    const uint8_t* __restrict__ flags,
+                                                   const uint32_t* __restrict__ smask,
+                                                   const uint32_t* __restrict__ mmask,
                                                    const float* __restrict__ ff, StepArgs a)
 {
     using T = typename St::raw_t;
@@ -417,16 +415,8 @@ __global__ __launch_bounds__(1024) void k_step_aa1(typename St::raw_t* f,
     for (int i = 0; i < Q; ++i) raw[i] = ld(plane(f, d, OPP[i], z), o);
 
     uint32_t mwmask = 0, solid = 0;
-    if (COLLIDE && ((fl & NEAR_MOVING) || (ONSITE && (fl & ONSITE_NODE)))) {
-        uint32_t on[Q];
-        pull_offsets(d, x, y, on);
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const uint8_t t = flags[src_slab(i, z, zm, zp) * d.nxy + on[i]] & TYPE_MASK;
-            if (t == MOVING) mwmask |= 1u << i;
-            if (t) solid |= 1u << i;
-        }
-    }
+    if (COLLIDE && (fl & NEAR_MOVING)) mwmask = mmask[c];
+    if (COLLIDE && ONSITE && (fl & ONSITE_NODE)) solid = smask[c];
     if (!COLLIDE) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) st(plane(f, d, i, z), o, raw[i]);
@@ -610,64 +600,65 @@ __global__ __launch_bounds__(256) void k_copy(const float* __restrict__ src, flo
 
 template <class St, int FM, bool ONSITE>
 static hipError_t step_fm(int pattern, int parity, bool collide, void* a, void* b,
-                          const uint8_t* flags, const float* ff, const StepArgs& args,
-                          const Launch& L, float* rho, float* u)
+                          const uint8_t* flags, const uint32_t* sm, const uint32_t* mm, const float* ff,
+                          const StepArgs& args, const Launch& L, float* rho, float* u)
 {
     using T = typename St::raw_t;
     T* A = static_cast<T*>(a);
     T* B = static_cast<T*>(b);
     if (pattern == 0) {
         if (collide && rho)
-            hipLaunchKernelGGL((k_step_ab<St, FM, true, true, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
+            hipLaunchKernelGGL((k_step_ab<St, FM, true, true, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
         else if (collide)
-            hipLaunchKernelGGL((k_step_ab<St, FM, true, false, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
+            hipLaunchKernelGGL((k_step_ab<St, FM, true, false, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
         else
-            hipLaunchKernelGGL((k_step_ab<St, FORCE_NONE, false, false, false>), L.grid, L.block, 0, L.stream, A, B, flags, ff, args, rho, u);
+            hipLaunchKernelGGL((k_step_ab<St, FORCE_NONE, false, false, false>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
     } else if (parity == 0) {
         if (collide)
-            hipLaunchKernelGGL((k_step_aa0<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
+            hipLaunchKernelGGL((k_step_aa0<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
         else
-            hipLaunchKernelGGL((k_step_aa0<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
+            hipLaunchKernelGGL((k_step_aa0<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
     } else {
         if (collide)
-            hipLaunchKernelGGL((k_step_aa1<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
+            hipLaunchKernelGGL((k_step_aa1<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
         else
-            hipLaunchKernelGGL((k_step_aa1<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, ff, args);
+            hipLaunchKernelGGL((k_step_aa1<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
     }
     return hipGetLastError();
 }
 
 template <class St, bool ONSITE>
 static hipError_t step_st(int pattern, int parity, bool collide, int fm, void* a, void* b,
-                          const uint8_t* flags, const float* ff, const StepArgs& args,
-                          const Launch& L, float* rho, float* u)
+                          const uint8_t* flags, const uint32_t* sm, const uint32_t* mm, const float* ff,
+                          const StepArgs& args, const Launch& L, float* rho, float* u)
 {
     switch (fm) {
-    case FORCE_UNIFORM: return step_fm<St, FORCE_UNIFORM, ONSITE>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
-    case FORCE_FIELD: return step_fm<St, FORCE_FIELD, ONSITE>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
-    default: return step_fm<St, FORCE_NONE, ONSITE>(pattern, parity, collide, a, b, flags, ff, args, L, rho, u);
+    case FORCE_UNIFORM: return step_fm<St, FORCE_UNIFORM, ONSITE>(pattern, parity, collide, a, b, flags, sm, mm, ff, args, L, rho, u);
+    case FORCE_FIELD: return step_fm<St, FORCE_FIELD, ONSITE>(pattern, parity, collide, a, b, flags, sm, mm, ff, args, L, rho, u);
+    default: return step_fm<St, FORCE_NONE, ONSITE>(pattern, parity, collide, a, b, flags, sm, mm, ff, args, L, rho, u);
     }
 }
 
 template <bool ONSITE>
 static hipError_t step_os(int storage, int pattern, int parity, bool collide, int force_mode, void* a,
-                          void* b, const uint8_t* flags, const float* ffield, const StepArgs& args,
-                          const Launch& L, float* rho, float* u)
+                          void* b, const uint8_t* flags, const uint32_t* sm, const uint32_t* mm,
+                          const float* ffield, const StepArgs& args, const Launch& L, float* rho, float* u)
 {
     switch (storage) {
-    case 1: return step_st<StF16, ONSITE>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
-    case 2: return step_st<StBF16, ONSITE>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
-    default: return step_st<StF32, ONSITE>(pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
+    case 1: return step_st<StF16, ONSITE>(pattern, parity, collide, force_mode, a, b, flags, sm, mm, ffield, args, L, rho, u);
+    case 2: return step_st<StBF16, ONSITE>(pattern, parity, collide, force_mode, a, b, flags, sm, mm, ffield, args, L, rho, u);
+    default: return step_st<StF32, ONSITE>(pattern, parity, collide, force_mode, a, b, flags, sm, mm, ffield, args, L, rho, u);
     }
 }
 
 hipError_t launch_step(int storage, int pattern, int parity, bool collide, int force_mode, void* a,
-                       void* b, const uint8_t* flags, const float* ffield, const StepArgs& args,
-                       const Launch& L, float* rho, float* u, bool onsite)
+                       void* b, const uint8_t* flags, const uint32_t* smask, const uint32_t* mmask,
+                       const float* ffield, const StepArgs& args, const Launch& L, float* rho, float* u,
+                       bool onsite)
 {
     return (onsite && collide)
-               ? step_os<true>(storage, pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u)
-               : step_os<false>(storage, pattern, parity, collide, force_mode, a, b, flags, ffield, args, L, rho, u);
+               ? step_os<true>(storage, pattern, parity, collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u)
+               : step_os<false>(storage, pattern, parity, collide, force_mode, a, b, flags, smask, mmask, ffield, args, L, rho, u);
 }
 
 template <class St, int FM, int VW, bool ONSITE, bool FLAT>

@@ -726,7 +726,7 @@ lbm_status lbm_adjoint(lbm_lattice* L, const float* g, float* gF, double* grad_t
                                                 L->d_smask, L->d_mmask, L->d_force, args, launch4_of(L)));
             else
                 HIPCHK(L, lbmk::launch_step(LBM_STORAGE_F32, LBM_PATTERN_AB, 0, true, fm, state(j - 1), state(j),
-                                            L->d_flags, L->d_force, args, LA));
+                                            L->d_flags, L->d_smask, L->d_mmask, L->d_force, args, LA));
         }
         for (int j = len - 1; j >= 0; --j) {
             if (vec)
@@ -776,11 +776,12 @@ lbm_status run_steps(lbm_lattice* L, int n, bool collide, float* rho, float* u)
             L->cur ^= 1;
         } else if (L->pattern == LBM_PATTERN_AB) {
             HIPCHK(L, lbmk::launch_step(L->storage, 0, 0, collide, fm, L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags,
-                                        L->d_force, args, LA, mr, mu, L->onsite));
+                                        L->d_smask, L->d_mmask, L->d_force, args, LA, mr, mu, L->onsite));
             L->cur ^= 1;
         } else {
             HIPCHK(L, lbmk::launch_step(L->storage, 1, L->parity, collide, fm, L->d_f[0], nullptr, L->d_flags,
-                                        L->d_force, args, LA, nullptr, nullptr, L->onsite));
+                                        L->d_smask, L->d_mmask, L->d_force, args, LA, nullptr, nullptr,
+                                        L->onsite));
             L->parity ^= 1;
         }
         ++L->steps_done;
