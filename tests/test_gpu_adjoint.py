@@ -34,6 +34,8 @@ CASES = {
     "random_moving": ((16, 8, 6), lambda s: W.random_flags(int(np.prod(s)), 7, 0.2, 0.05),
                       (0.03, -0.01, 0.02), 5e-4, 0.65),
     "periodic": ((8, 6, 5), lambda s: np.zeros(int(np.prod(s)), np.uint8), (0, 0, 0), 1e-3, 1.1),
+    # 65 four-point groups per row: the forward recompute on the one-dimensional grid
+    "wide_rows": ((260, 4, 3), lambda s: W.duct_flags(*s), (0, 0, 0), 1e-3, 0.7),
 }
 
 
@@ -92,7 +94,7 @@ def test_checkpoint_spacing_does_not_change_gradients():
         assert got[1] == ref[1]
 
 
-@pytest.mark.parametrize("name", ["duct_x4", "random_moving", "periodic"])
+@pytest.mark.parametrize("name", ["duct_x4", "random_moving", "periodic", "wide_rows"])
 def test_vector_reverse_step_equals_one_point_reverse_step(name):
     """The two-points-per-work-item reverse step (and the four-point forward
     recompute) run the same per-point arithmetic as the one-point kernels:
