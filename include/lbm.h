@@ -244,8 +244,10 @@ const char* lbm_last_error(void);
 /*
  * Bandwidth probe used to state the measured copy ceiling of the device
  * (the paper quotes measured rather than nominal bandwidth, Section 2.2):
- * dst[k] = src[k] for k < n floats, on the given stream, with the same
- * one-element-per-work-item shape as the step kernels.
+ * dst[k] = src[k] for k < n floats (device pointers, 16-byte aligned, not
+ * overlapping), on the given stream: one 16-byte chunk per work-item with
+ * non-temporal loads and stores, like the vector step's accesses.
+ * LBM_ERR_INVALID for a NULL or misaligned pointer with n > 0.
  */
 lbm_status lbm_copy_f32(const float* src_dev, float* dst_dev, size_t n, void* hip_stream);
 

@@ -582,17 +582,23 @@ __global__ __launch_bounds__(1024) void k_mark_near_wall(const uint8_t* __restri
     mmask[c] = mm;
 }
 
-// Bandwidth probe: one 16-byte load and one 16-byte store per work-item, the
-// store non-temporal like the vector step's stores.
+// Bandwidth probe: one 16-byte chunk per work-item (src and dst 16-byte
+// aligned), load and store both non-temporal: the fastest plain copy
+// measured on MI355X (2 GiB of random data: 6.46 TB/s, against 6.28 with
+// only the store hinted and 6.16 with neither; two or more chunks per
+// work-item were slower). The work-item after the last whole chunk copies
+// the 0-3 remaining floats.
 __global__ __launch_bounds__(256) void k_copy(const float* __restrict__ src, float* __restrict__ dst,
                                               size_t n)
 {
-    const size_t k = 4 * ((size_t)blockIdx.x * blockDim.x + threadIdx.x);
-    if (k + 4 <= n) {
-        __builtin_nontemporal_store(*reinterpret_cast<const typename V4<float>::t*>(src + k),
-                                    reinterpret_cast<typename V4<float>::t*>(dst + k));
-    } else {
-        for (size_t e = k; e < n; ++e) dst[e] = src[e];
+    using F4 = typename V4<float>::t;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t n4 = n / 4;
+    if (k < n4) {
+        __builtin_nontemporal_store(__builtin_nontemporal_load(reinterpret_cast<const F4*>(src) + k),
+                                    reinterpret_cast<F4*>(dst) + k);
+    } else if (k == n4) {
+        for (size_t e = 4 * n4; e < n; ++e) dst[e] = src[e];
     }
 }
 
@@ -851,7 +857,7 @@ hipError_t launch_check_finite(int storage, int layout, const void* f, const uin
 hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    const size_t blocks = ((n + 3) / 4 + 255) / 256;
+    const size_t blocks = (n / 4 + 1 + 255) / 256;   // whole chunks plus the tail work-item
     hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
     return hipGetLastError();
 }

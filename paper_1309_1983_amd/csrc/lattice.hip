@@ -620,6 +620,7 @@ lbm_status lbm_step_times(lbm_lattice* L, float* ms, int cap, int* count)
 lbm_status lbm_copy_f32(const float* src, float* dst, size_t n, void* stream)
 {
     if ((!src || !dst) && n) return fail(LBM_ERR_INVALID, "NULL buffer");
+    if (n && (((uintptr_t)src | (uintptr_t)dst) & 15u)) return fail(LBM_ERR_INVALID, "buffers must be 16-byte aligned");
     hipError_t e = lbmk::launch_copy(src, dst, n, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail(LBM_ERR_DEVICE, "copy: %s", hipGetErrorString(e));
     return LBM_OK;

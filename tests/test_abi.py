@@ -118,6 +118,16 @@ def test_calls_on_null_lattice(abi):
     L.lbm_destroy(None)  # no-op
 
 
+def test_copy_probe_rejects_null_and_misaligned_buffers(abi):
+    # validated before any HIP call, so this runs without a GPU
+    L = abi.lib()
+    n = ctypes.c_size_t(8)
+    assert L.lbm_copy_f32(None, None, n, None) == abi.LBM_ERR_INVALID
+    assert L.lbm_copy_f32(ctypes.c_void_p(4096 + 4), ctypes.c_void_p(8192), n, None) == abi.LBM_ERR_INVALID
+    assert "aligned" in abi.last_error()
+    assert L.lbm_copy_f32(ctypes.c_void_p(4096), ctypes.c_void_p(8192 + 8), n, None) == abi.LBM_ERR_INVALID
+
+
 def test_study_calls_reject_bad_arguments(abi):
     L = abi.lib()
     assert L.lbm_study_stream(0, None, None, None, 1024, 19, 0, 0, 4, None) == abi.LBM_ERR_INVALID
