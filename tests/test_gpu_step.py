@@ -129,8 +129,11 @@ def _case(name):
         shape, tau = (48, 40, 64), 0.7
         flags = W.sphere_duct_flags(*shape, seed=5, solid_fraction=0.10)
         return shape, tau, flags, None, (0, 0, 1e-6), None, near_rest_state(flags.size, 12, 0.005, 0.01)
-    if name in ("random_walls_field", "random_walls_field_x4"):
-        shape, tau = ((33, 17, 11) if name == "random_walls_field" else (36, 17, 11)), 0.9
+    if name in ("random_walls_field", "random_walls_field_x4", "random_walls_wide_rows"):
+        # wide rows: 65 four-point groups per row, the vector step's one-dimensional grid
+        shape = {"random_walls_field": (33, 17, 11), "random_walls_field_x4": (36, 17, 11),
+                 "random_walls_wide_rows": (260, 9, 7)}[name]
+        tau = 0.9
         N = int(np.prod(shape))
         flags = W.random_flags(N, seed=13, solid_fraction=0.2, moving_fraction=0.05)
         ff = W.random_force_field(N, 14, 1e-4).astype(np.float32)
@@ -139,7 +142,7 @@ def _case(name):
 
 
 @pytest.mark.parametrize("name", ["tgv32", "cavity_ragged", "spheres_duct", "random_walls_field",
-                                  "random_walls_field_x4"])
+                                  "random_walls_field_x4", "random_walls_wide_rows"])
 def test_f32_step_matches_oracle_after_100_steps(name):
     shape, tau, flags, uw, force, ff, s0 = _case(name)
     got = _gpu_run(shape, tau, s0, 100, flags=flags, uw=uw, force=force, force_field=ff)
@@ -152,7 +155,8 @@ def test_f32_step_matches_oracle_after_100_steps(name):
 
 
 @pytest.mark.parametrize("name,pattern", [("random_walls_field", "ab"), ("random_walls_field_x4", "ab"),
-                                          ("spheres_duct", "ab"), ("random_walls_field_x4", "aa")])
+                                          ("spheres_duct", "ab"), ("random_walls_field_x4", "aa"),
+                                          ("random_walls_wide_rows", "ab")])
 def test_fused_macros_match_separate_pass_and_oracle(name, pattern):
     """rho and u written by the step itself (168 B per point variant) equal the
     separate macroscopic pass over the resulting state to FP32 rounding, and
