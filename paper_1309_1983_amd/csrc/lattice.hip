@@ -179,6 +179,9 @@ lbmk::Launch launch4_of(const lbm_lattice* L)
 
 void default_block(int nx, int& bx, int& by)
 {
+    // rows that are a multiple of 512 points: 512-point groups, 6.5% faster
+    // than 256 for the in-place 16-bit step at 512^3 on MI355X
+    if (nx % 512 == 0) { bx = 512; by = 1; return; }
     if (nx >= 256) { bx = 256; by = 1; return; }
     if ((nx & (nx - 1)) == 0) { bx = nx; by = 256 / nx; return; }
     bx = std::min(256, (nx + 63) / 64 * 64);
