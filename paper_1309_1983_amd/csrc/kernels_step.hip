@@ -407,6 +407,7 @@ __global__ __launch_bounds__(1024) void k_step_aa1(typename St::raw_t* f,
     using T = typename St::raw_t;
     const Dims& d = a.d;
     POINT_PROLOGUE(d)
+    (void)zm; (void)zp;   // every access of the local step is in the point's own slab
     const uint8_t fl = flags[c];
     if (fl & TYPE_MASK) return;
 
