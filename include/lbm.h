@@ -104,7 +104,33 @@ typedef struct lbm_options {
                              nx to be a multiple of them and
                              block_x * block_y <= 256 (block_x then counts
                              work-items) */
+    int gather_mode;      /* FP32 multi-point AB step: 0 = automatic (early
+                             gather when at least 8% of the fluid points have a
+                             solid neighbour), 1 = flags first, 2 = early
+                             gather (the 19 loads are issued before the point
+                             flags are examined). Results are identical. */
+    void* population_dev[2]; /* optional caller-owned device buffers for the
+                             population arrays: both NULL = the library
+                             allocates them; otherwise the AB pattern needs
+                             both and AA the first, each of at least
+                             lbm_buffer_sizes().population_bytes, 256-byte
+                             aligned, not overlapping, alive and unused by
+                             the caller until lbm_destroy returns. The
+                             library never frees them and lbm_device_bytes
+                             does not count them. */
 } lbm_options;
+
+/* Device memory a lattice of the given size and options needs (Section 4.1:
+ * 19 populations per point). population_bytes: one population array (the AB
+ * pattern uses two, AA one); adjoint_bytes: the workspace of lbm_adjoint
+ * (two adjoint arrays and per-work-group partial sums); state_bytes: one FP32
+ * state [19][N], the unit of the checkpoint store. */
+typedef struct lbm_buffer_sizes {
+    size_t population_bytes;
+    int population_arrays;
+    size_t adjoint_bytes;
+    size_t state_bytes;
+} lbm_buffer_sizes;
 
 typedef struct lbm_lattice lbm_lattice;
 
@@ -132,14 +158,48 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
                          const lbm_options* opt, lbm_lattice** out);
 
 /* Releases everything the library allocated for the lattice (after waiting
- * for its stream). NULL is a no-op. */
+ * for its stream). NULL is a no-op. Caller-owned buffers (population_dev,
+ * lbm_set_trajectory_buffer, lbm_set_adjoint_buffer) are not freed; they may
+ * be released once this returns. */
 void lbm_destroy(lbm_lattice* lat);
+
+/* Sizes of the device buffers a lattice of nx*ny*nz points created with
+ * `opt` (NULL: defaults) uses, so that a caller can allocate them itself
+ * (population_dev in lbm_options, lbm_set_adjoint_buffer). Nothing is
+ * allocated. Errors: LBM_ERR_INVALID for the arguments lbm_create_ex rejects
+ * before touching the device. */
+lbm_status lbm_query_buffer_sizes(int nx, int ny, int nz, const lbm_options* opt, lbm_buffer_sizes* out);
+
+/* Bytes of the checkpoint store lbm_forward_checkpointed(T, K) uses on a
+ * lattice of nx*ny*nz points: ceil(T/K) checkpoints plus min(K, T) - 1
+ * recomputed states (at least one checkpoint), each state_bytes. 0 for
+ * invalid arguments. */
+size_t lbm_trajectory_bytes(int nx, int ny, int nz, int T, int K);
+
+/* Gives the lattice a caller-owned device buffer for the checkpoint store of
+ * lbm_forward_checkpointed (`bytes` long, 256-byte aligned). Later rollouts
+ * whose lbm_trajectory_bytes exceeds `bytes` fail with LBM_ERR_INVALID instead
+ * of allocating. NULL returns to library-allocated storage. Drops a recorded
+ * trajectory. The buffer must stay alive and untouched by the caller until
+ * it is replaced or the lattice is destroyed. */
+lbm_status lbm_set_trajectory_buffer(lbm_lattice* lat, void* dev, size_t bytes);
+
+/* Gives the lattice a caller-owned device workspace for lbm_adjoint of at
+ * least lbm_buffer_sizes().adjoint_bytes (256-byte aligned); NULL returns to
+ * library-allocated storage (allocated at the first lbm_adjoint). The buffer
+ * must stay alive and untouched by the caller until it is replaced or the
+ * lattice is destroyed. Errors: LBM_ERR_INVALID if `bytes` is too small or
+ * the pointer misaligned. */
+lbm_status lbm_set_adjoint_buffer(lbm_lattice* lat, void* dev, size_t bytes);
 
 /* Lattice sizes and storage, for the caller's bookkeeping. */
 lbm_status lbm_get_info(const lbm_lattice* lat, int* nx, int* ny, int* nz, int* storage,
                         int* pattern);
 
-/* Changes the stream later work is launched on (NULL = null stream). */
+/* Changes the stream later work is launched on (NULL = null stream). Work
+ * already enqueued on the previous stream is ordered before later work on the
+ * new one (an event recorded on the old stream is waited for on the new one;
+ * the host does not block). */
 lbm_status lbm_set_stream(lbm_lattice* lat, void* hip_stream);
 
 /* Relaxation time (Eq. (2)); tau > 0.5. Invalidates a recorded trajectory. */
@@ -183,17 +243,22 @@ lbm_status lbm_step_macros(lbm_lattice* lat, int n, float* rho_dev, float* u_dev
  * get rho = 0, u = 0. Either pointer may be NULL to skip it, not both. */
 lbm_status lbm_macros(lbm_lattice* lat, float* rho_dev, float* u_dev);
 
-/* Copies the state out as plain populations f[19][N] float (offsets added
- * back, the AA layout resolved). */
+/* Copies the state out as plain populations f_dev [19][N] float in the
+ * structure-of-arrays order of Section 4.1 (element i*N + c; offsets added
+ * back, the AA layout resolved, whatever the internal plane layout).
+ * Errors: LBM_ERR_INVALID for NULL. */
 lbm_status lbm_get_populations(lbm_lattice* lat, float* f_dev);
 
-/* Replaces the state with f_dev [19][N] float (plain populations; 16-bit
- * storage rounds the offsets). Invalidates a recorded trajectory. */
+/* Replaces the state with f_dev [19][N] float, plain populations in the order
+ * of lbm_get_populations (16-bit storage rounds the offsets to nearest even).
+ * Invalidates a recorded trajectory. Errors: LBM_ERR_INVALID for NULL. */
 lbm_status lbm_set_populations(lbm_lattice* lat, const float* f_dev);
 
-/* Test hook: n steps of pull streaming with bounce-back and no collision
- * and no moving-wall term (an exact permutation of the stored values);
- * on-site nodes stream like plain fluid points here. */
+/* Test hook: n steps of the streaming half of Algorithm 3 alone (the pull of
+ * Section 4.2 with bounce-back at solid neighbours, no collision and no
+ * moving-wall term): an exact permutation of the stored values. On-site
+ * nodes stream like plain fluid points here. Errors: LBM_ERR_INVALID for
+ * n < 0. */
 lbm_status lbm_debug_stream_only(lbm_lattice* lat, int n);
 
 /*
@@ -226,7 +291,10 @@ lbm_status lbm_check_finite(lbm_lattice* lat);
 
 /* Per-step durations (ms) of the most recent steps recorded with
  * timing_capacity > 0, oldest first: at most cap values into ms_host,
- * *count = number written. Synchronises. Clears the log. */
+ * *count = number written. This is the iteration-time series whose spread
+ * and periodic components Section 6 (Table 5) analyses. Synchronises.
+ * Clears the log. Errors: LBM_ERR_STATE without a timing log;
+ * LBM_ERR_INVALID for bad output arguments. */
 lbm_status lbm_step_times(lbm_lattice* lat, float* ms_host, int cap, int* count);
 
 /* Waits for all work enqueued on the lattice's stream. */

@@ -16,7 +16,8 @@ PATTERN = {"ab": 0, "aa": 1}
 
 # Every symbol the header declares, in header order.
 EXPORTS = [
-    "lbm_options_default", "lbm_create", "lbm_create_ex", "lbm_destroy", "lbm_get_info",
+    "lbm_options_default", "lbm_create", "lbm_create_ex", "lbm_destroy", "lbm_query_buffer_sizes",
+    "lbm_trajectory_bytes", "lbm_set_trajectory_buffer", "lbm_set_adjoint_buffer", "lbm_get_info",
     "lbm_set_stream", "lbm_set_tau", "lbm_set_wall_velocity", "lbm_set_force_uniform",
     "lbm_set_force_field", "lbm_init_equilibrium", "lbm_step", "lbm_step_macros", "lbm_macros",
     "lbm_get_populations", "lbm_set_populations", "lbm_debug_stream_only",
@@ -44,6 +45,17 @@ class lbm_options(ctypes.Structure):
         ("check_interval", ctypes.c_int),
         ("device", ctypes.c_int),
         ("cells_per_lane", ctypes.c_int),
+        ("gather_mode", ctypes.c_int),
+        ("population_dev", ctypes.c_void_p * 2),
+    ]
+
+
+class lbm_buffer_sizes(ctypes.Structure):
+    _fields_ = [
+        ("population_bytes", ctypes.c_size_t),
+        ("population_arrays", ctypes.c_int),
+        ("adjoint_bytes", ctypes.c_size_t),
+        ("state_bytes", ctypes.c_size_t),
     ]
 
 
@@ -72,6 +84,11 @@ def lib():
         "lbm_create": (c_int, [c_int, c_int, c_int, c_float, vp, pp]),
         "lbm_create_ex": (c_int, [c_int, c_int, c_int, c_float, vp, ctypes.POINTER(lbm_options), pp]),
         "lbm_destroy": (None, [vp]),
+        "lbm_query_buffer_sizes": (c_int, [c_int, c_int, c_int, ctypes.POINTER(lbm_options),
+                                           ctypes.POINTER(lbm_buffer_sizes)]),
+        "lbm_trajectory_bytes": (c_size, [c_int, c_int, c_int, c_int, c_int]),
+        "lbm_set_trajectory_buffer": (c_int, [vp, vp, c_size]),
+        "lbm_set_adjoint_buffer": (c_int, [vp, vp, c_size]),
         "lbm_get_info": (c_int, [vp, ip, ip, ip, ip, ip]),
         "lbm_set_stream": (c_int, [vp, vp]),
         "lbm_set_tau": (c_int, [vp, c_float]),

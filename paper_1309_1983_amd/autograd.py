@@ -1,7 +1,8 @@
 """torch.autograd glue over the library's checkpointed rollout and adjoint.
 
 rollout(lattice, force, tau, T, K) runs T steps from the lattice's current
-state with the per-point body force `force` [3, N] and relaxation time `tau`,
+state with the per-point body force `force` (3*N values, component slowest:
+[3, N] or [3, nz, ny, nx]) and relaxation time `tau`,
 and returns u(T) [3, N]. Its backward calls the library's reverse sweep
 (lbm_adjoint) and returns dL/dforce and dL/dtau. The forward and reverse
 arithmetic all run in the HIP kernels; this module only moves tensors.
@@ -22,6 +23,8 @@ class _Rollout(torch.autograd.Function):
         lattice.forward_checkpointed(T, K)
         _, u = lattice.macros()
         ctx.lattice = lattice
+        ctx.force_shape = force.shape
+        ctx.force_dtype = force.dtype
         ctx.tau_dtype = tau.dtype
         ctx.tau_device = tau.device
         return u
@@ -31,7 +34,7 @@ class _Rollout(torch.autograd.Function):
         lat: Lattice = ctx.lattice
         gF, gtau = lat.adjoint(grad_u.contiguous())
         gt = torch.tensor(gtau, dtype=ctx.tau_dtype, device=ctx.tau_device)
-        return gF, gt, None, None, None, None
+        return gF.reshape(ctx.force_shape).to(ctx.force_dtype), gt, None, None, None, None
 
 
 def rollout(lattice: Lattice, force: torch.Tensor, tau: torch.Tensor, T: int, K: int,
@@ -41,6 +44,10 @@ def rollout(lattice: Lattice, force: torch.Tensor, tau: torch.Tensor, T: int, K:
     s0: initial populations [19, N] (default: the lattice's current state).
     Needs F32 storage and the AB pattern.
     """
+    if force.numel() != 3 * lattice.N:
+        raise ValueError(f"force must be a per-point field of 3*N = {3 * lattice.N} values (component "
+                         f"slowest, e.g. [3, N]); got shape {tuple(force.shape)}. A uniform force is a "
+                         f"field with equal values; its gradient is the sum of the field's.")
     if s0 is None:
         s0 = lattice.populations()
     return _Rollout.apply(force, tau, lattice, int(T), int(K), s0)

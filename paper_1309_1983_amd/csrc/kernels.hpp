@@ -20,6 +20,8 @@ struct StepArgs {
     uint32_t gx;                // vector AB step: > 0 = its grid is one-dimensional in x over
                                 // the gx * ny point groups of a z-plane (gx = nx / vw groups
                                 // per row, x fastest); 0 = two-dimensional (x groups, y)
+    uint32_t early;             // FP32 vector AB step: issue the gather before the flag
+                                // branches (porous geometry)
 };
 
 struct Launch {
@@ -54,8 +56,10 @@ hipError_t launch_step_abv(int storage, int vw, bool collide, int force_mode, vo
 // solid / moving-wall cell and ONSITE / ONSITE_MOVING; smask / mmask bit i
 // set when x - e_i is solid / a moving wall. *bad |= 1 for an on-site node
 // whose solid neighbours do not form a box face, edge or corner.
+// counts[0] += fluid points with a solid neighbour, counts[1] += fluid points.
 hipError_t launch_mark_near_wall(const uint8_t* flags_in, uint8_t* flags_out, uint32_t* smask,
-                                 uint32_t* mmask, int* bad, const d3q19::Dims& d, const Launch& L);
+                                 uint32_t* mmask, int* bad, unsigned* counts, const d3q19::Dims& d,
+                                 const Launch& L);
 
 // f = f^eq(rho, u) in the given storage (natural layout).
 hipError_t launch_init_eq(int storage, void* f, const float* rho, const float* u,

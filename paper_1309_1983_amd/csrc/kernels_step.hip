@@ -176,8 +176,23 @@ struct FlagWord<8> {
     static constexpr uint64_t ones = 0x0101010101010101ull;
 };
 
-template <class St, int FM, bool COLLIDE, int VW, bool MACROS, bool ONSITE, bool FLAT>
-__global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __restrict__ src,
+// EARLY (FP32, porous geometry): the gather's loads are issued before the
+// flag-dependent branches (gather_vec), with the neighbour masks of every
+// work-item; fully solid groups then run the whole path and store the rest
+// state like solid points in mixed groups, and waves with no fluid point
+// store nothing.
+template <class St, int VW, bool ONSITE>
+struct Occupancy {
+    // Waves per SIMD the register budget must allow: the 16-bit eight-point
+    // step sits at the 168-VGPR edge of three waves per SIMD, and losing the
+    // third wave cost 11% at 256^3 on MI355X; the on-site variants need more
+    // registers than three waves allow and keep two.
+    static constexpr int waves = (VW == 8 && !ONSITE) ? 3 : 1;
+};
+
+template <class St, int FM, bool COLLIDE, int VW, bool MACROS, bool ONSITE, bool FLAT, bool EARLY>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<St, VW, ONSITE>::waves)))
+void k_step_abv(const typename St::bits_t* __restrict__ src,
                                                   typename St::bits_t* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
                                                   const uint32_t* __restrict__ smask,
@@ -209,19 +224,25 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
     const uint32_t orow = (uint32_t)y * nx;
     const uint32_t o0 = orow + (uint32_t)x0;
     const uint32_t c0 = z * d.nxy + o0;
+    static_assert(!EARLY || (sizeof(B) == 4 && !MACROS && !ONSITE && COLLIDE), "early gather: FP32 step only");
     const FW flw = *reinterpret_cast<const FW*>(flags + c0);
     const FW solid = (flw | (flw >> 1)) & ONES;   // byte j: point j solid
-    // wave-wide vote, taken by every work-item before the branch
-    const bool wave_fluid = __builtin_amdgcn_ballot_w64(solid != ONES) != 0ull;
-    if (solid == ONES) {
-        if (MACROS) {
-            const typename Vec<float, VW>::t zero = 0.0f;
-            stv_nt<VW>(rho_out, c0, zero);
+    uint32_t early_mask[EARLY ? VW : 1];
+    if constexpr (EARLY) {
+        load_words<VW>(smask, c0, early_mask);
+    } else {
+        // wave-wide vote, taken by every work-item before the branch
+        const bool wave_fluid = __builtin_amdgcn_ballot_w64(solid != ONES) != 0ull;
+        if (solid == ONES) {
+            if (MACROS) {
+                const typename Vec<float, VW>::t zero = 0.0f;
+                stv_nt<VW>(rho_out, c0, zero);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) stv_nt<VW>(u_out + k * (size_t)d.N, c0, zero);
+                for (int k = 0; k < 3; ++k) stv_nt<VW>(u_out + k * (size_t)d.N, c0, zero);
+            }
+            if (wave_fluid) store_rest<St, VW>(dst, d, z, o0);
+            return;
         }
-        if (wave_fluid) store_rest<St, VW>(dst, d, z, o0);
-        return;
     }
 
     const uint32_t zm = wrap_m(z, (uint32_t)d.nz), zp = wrap_p(z, (uint32_t)d.nz);
@@ -229,8 +250,9 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
     const uint32_t oyp = (y == d.ny - 1) ? (uint32_t)(1 - d.ny) * nx : nx;
 
     Vt q[Q];
-    gather_vec<+1, VW>(src, d, z, zm, zp, orow, oym, oyp, (uint32_t)x0, !(solid & 0x1u),
-                       !((solid >> (8 * (VW - 1))) & 0x1u), (flw & (ONES * NEAR_WALL)) != 0, smask, c0, q);
+    gather_vec<+1, VW, EARLY>(src, d, z, zm, zp, orow, oym, oyp, (uint32_t)x0, !(solid & 0x1u),
+                              !((solid >> (8 * (VW - 1))) & 0x1u), (flw & (ONES * NEAR_WALL)) != 0, smask, c0,
+                              q, early_mask);
 
     // moving-wall terms of the bounced populations
     uint32_t mm[VW];
@@ -341,6 +363,9 @@ __global__ __launch_bounds__(256) void k_step_abv(const typename St::bits_t* __r
             stv_nt<VW>(u_out + (size_t)d.N, c0, my);
             stv_nt<VW>(u_out + 2 * (size_t)d.N, c0, mz);
         }
+    }
+    if constexpr (EARLY) {
+        if (__builtin_amdgcn_ballot_w64(solid != ONES) == 0ull) return;   // no fluid point in the wave
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) stv_nt<VW>(plane(dst, d, i, z), o0, q[i]);
@@ -550,11 +575,14 @@ __global__ __launch_bounds__(1024) void k_check_finite(const typename St::raw_t*
 // are solid; on-site nodes (3, 4) are fluid nodes.
 __device__ __forceinline__ uint8_t type_of(uint8_t v) { return (v == 1 || v == 2) ? v : 0; }
 
+// counts[0] += fluid points with a solid neighbour, counts[1] += fluid
+// points (one atomic per wave).
 __global__ __launch_bounds__(1024) void k_mark_near_wall(const uint8_t* __restrict__ in,
                                                          uint8_t* __restrict__ out,
                                                          uint32_t* __restrict__ smask,
                                                          uint32_t* __restrict__ mmask,
-                                                         int* __restrict__ bad, Dims d)
+                                                         int* __restrict__ bad,
+                                                         unsigned* __restrict__ counts, Dims d)
 {
     POINT_PROLOGUE(d)
     const uint8_t v = in[c];
@@ -581,6 +609,13 @@ __global__ __launch_bounds__(1024) void k_mark_near_wall(const uint8_t* __restri
     out[c] = r;
     smask[c] = sm;
     mmask[c] = mm;
+    const uint64_t near = __builtin_amdgcn_ballot_w64(fl == 0 && sm != 0u);
+    const uint64_t fluid = __builtin_amdgcn_ballot_w64(fl == 0);
+    const uint64_t active = __builtin_amdgcn_read_exec();
+    if (__lane_id() == (unsigned)__builtin_ctzll(active)) {
+        if (near) atomicAdd(&counts[0], (unsigned)__builtin_popcountll(near));
+        if (fluid) atomicAdd(&counts[1], (unsigned)__builtin_popcountll(fluid));
+    }
 }
 
 // Bandwidth probe: one 16-byte chunk per work-item (src and dst 16-byte
@@ -676,12 +711,15 @@ static hipError_t stepv_grid(bool collide, void* a, void* b, const uint8_t* flag
     using B = typename St::bits_t;
     const B* A = static_cast<const B*>(a);
     B* Bp = static_cast<B*>(b);
+    constexpr bool CAN_EARLY = sizeof(B) == 4 && !ONSITE;
     if (collide && rho)
-        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, true, ONSITE, FLAT>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, true, ONSITE, FLAT, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+    else if (collide && CAN_EARLY && args.early)
+        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, false, ONSITE, FLAT, CAN_EARLY>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     else if (collide)
-        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, false, ONSITE, FLAT>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, false, ONSITE, FLAT, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     else
-        hipLaunchKernelGGL((k_step_abv<St, FORCE_NONE, false, VW, false, false, FLAT>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        hipLaunchKernelGGL((k_step_abv<St, FORCE_NONE, false, VW, false, false, FLAT, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     return hipGetLastError();
 }
 
@@ -734,9 +772,9 @@ hipError_t launch_step_abv(int storage, int vw, bool collide, int force_mode, vo
 }
 
 hipError_t launch_mark_near_wall(const uint8_t* in, uint8_t* out, uint32_t* smask, uint32_t* mmask, int* bad,
-                                 const Dims& d, const Launch& L)
+                                 unsigned* counts, const Dims& d, const Launch& L)
 {
-    hipLaunchKernelGGL(k_mark_near_wall, L.grid, L.block, 0, L.stream, in, out, smask, mmask, bad, d);
+    hipLaunchKernelGGL(k_mark_near_wall, L.grid, L.block, 0, L.stream, in, out, smask, mmask, bad, counts, d);
     return hipGetLastError();
 }
 

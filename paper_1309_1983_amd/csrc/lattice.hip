@@ -60,6 +60,7 @@ struct lbm_lattice {
     bool has_force_field = false;
 
     void* d_f[2] = {nullptr, nullptr};
+    bool own_f = true;             // population arrays allocated by the library
     int cur = 0;      // AB: index of the array holding the state
     int parity = 0;   // AA: 0 natural layout, 1 shifted layout
     uint8_t* d_flags = nullptr;
@@ -71,6 +72,8 @@ struct lbm_lattice {
     int bx4 = 64, by4 = 1;         // work-group of the vector kernel
     bool flat = false;             // vector AB step on a one-dimensional grid per plane
     bool onsite = false;           // has on-site velocity nodes (flags 3, 4)
+    bool early = false;            // FP32 vector AB step gathers before the flag branches
+    hipEvent_t order_ev = nullptr; // orders work across lbm_set_stream
 
     bool sticky = false;
     long long steps_done = 0;
@@ -88,9 +91,14 @@ struct lbm_lattice {
     long long version = 0;           // bumped by anything that changes the dynamics/state
     float* d_seg = nullptr;          // (K-1) states
     int seg_cap = 0;
+    void* traj_dev = nullptr;        // caller-owned checkpoint store (NULL: library allocates)
+    size_t traj_bytes = 0;
+    bool traj_owned = true;          // ckpt / d_seg were allocated by the library
     float* d_adj[2] = {nullptr, nullptr};
     double* d_taupart = nullptr;
     size_t taupart_n = 0;
+    void* adj_dev = nullptr;         // caller-owned adjoint workspace (NULL: library allocates)
+    size_t adj_bytes = 0;
 
     size_t bytes = 0;
 };
@@ -156,6 +164,7 @@ lbmk::StepArgs step_args(const lbm_lattice* L)
     }
     for (int k = 0; k < 3; ++k) a.uw[k] = L->uw[k];
     a.gx = L->flat ? (uint32_t)(L->nx / L->cpl) : 0u;
+    a.early = L->early ? 1u : 0u;
     return a;
 }
 
@@ -188,6 +197,50 @@ void default_block(int nx, int& bx, int& by)
     by = std::max(1, 256 / bx);
 }
 
+// Work-group shape of the one-point reverse step: the default shape capped at
+// the kernel's 256 work-items (rows that are a multiple of 512 points take
+// 512-point groups for the forward steps).
+void adjoint_block(int nx, int& bx, int& by)
+{
+    default_block(nx, bx, by);
+    if (bx * by > 256) {
+        bx = std::min(bx, 256);
+        by = std::max(1, 256 / bx);
+    }
+}
+
+// Launch of the reverse step: two x-points per work-item with 64-work-item
+// groups (the fastest shape measured at 256^3; four points need too many
+// registers), else one point per work-item with at most 256 per group.
+lbmk::Launch adjoint_launch(const d3q19::Dims& dims, bool vec_ok, hipStream_t stream, bool& vec)
+{
+    vec = vec_ok && dims.nx % 2 == 0;
+    if (vec) {
+        d3q19::Dims q = dims;
+        q.nx = dims.nx / 2;
+        const int rbx = std::min(q.nx, 64);
+        return lbmk::make_launch(q, rbx, std::max(1, 64 / rbx), stream);
+    }
+    int abx, aby;
+    adjoint_block(dims.nx, abx, aby);
+    return lbmk::make_launch(dims, abx, aby, stream);
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t state_bytes_of(size_t N) { return (size_t)Q * N * sizeof(float); }
+
+// Adjoint workspace: two adjoint arrays, then one double per work-group.
+size_t adjoint_bytes_of(const d3q19::Dims& dims, bool vec_ok, size_t& nblk)
+{
+    bool vec = false;
+    const lbmk::Launch LR = adjoint_launch(dims, vec_ok, nullptr, vec);
+    nblk = (size_t)LR.grid.x * LR.grid.y * LR.grid.z;
+    return 2 * round256(state_bytes_of(dims.N)) + nblk * sizeof(double);
+}
+
+bool aligned256(const void* p) { return ((uintptr_t)p & 255u) == 0; }
+
 template <class T>
 lbm_status dalloc(lbm_lattice* L, T** p, size_t bytes, const char* what)
 {
@@ -214,13 +267,30 @@ void dfree(lbm_lattice* L, void* p, size_t bytes)
 void drop_trajectory(lbm_lattice* L)
 {
     const size_t sb = (size_t)Q * L->N * sizeof(float);
-    for (float* p : L->ckpt) dfree(L, p, sb);
+    if (L->traj_owned) {
+        for (float* p : L->ckpt) dfree(L, p, sb);
+        dfree(L, L->d_seg, sb * (size_t)L->seg_cap);
+    }
     L->ckpt.clear();
-    dfree(L, L->d_seg, sb * (size_t)L->seg_cap);
     L->d_seg = nullptr;
     L->seg_cap = 0;
     L->traj_T = -1;
     L->traj_version = -1;
+}
+
+// Releases library-allocated adjoint buffers; caller workspace pointers are
+// just forgotten.
+void drop_adjoint_buffers(lbm_lattice* L)
+{
+    const size_t sb = state_bytes_of(L->N);
+    if (!L->adj_dev) {
+        dfree(L, L->d_adj[0], sb);
+        dfree(L, L->d_adj[1], sb);
+        dfree(L, L->d_taupart, L->taupart_n * sizeof(double));
+    }
+    L->d_adj[0] = L->d_adj[1] = nullptr;
+    L->d_taupart = nullptr;
+    L->taupart_n = 0;
 }
 
 void invalidate(lbm_lattice* L) { ++L->version; }
@@ -260,22 +330,29 @@ lbm_status lbm_create(int nx, int ny, int nz, float tau, const uint8_t* flags_ho
     return lbm_create_ex(nx, ny, nz, tau, flags_host, nullptr, out);
 }
 
-lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags_host,
-                         const lbm_options* opt_in, lbm_lattice** out)
+}  // extern "C"
+
+namespace {
+
+// Launch layout of a lattice, resolved from its size and options.
+struct Layout {
+    int bx = 0, by = 0;        // one-point kernels
+    int cpl = 1;               // points per work-item of the AB step
+    int bx4 = 0, by4 = 0;      // vector AB step work-group
+    bool flat = false;         // vector AB step on a one-dimensional grid per plane
+};
+
+// Validates everything lbm_create_ex checks before touching the device
+// except tau and the flags, and resolves the launch layout.
+lbm_status resolve_layout(int nx, int ny, int nz, const lbm_options& opt, Layout& lay)
 {
-    g_last_error.clear();
-    if (!out) return fail(LBM_ERR_INVALID, "out is NULL");
-    *out = nullptr;
     if (nx <= 0 || ny <= 0 || nz <= 0) return fail(LBM_ERR_INVALID, "sizes must be positive (%d,%d,%d)", nx, ny, nz);
     const unsigned long long N = (unsigned long long)nx * ny * nz;
     if (N >= (1ull << 30)) return fail(LBM_ERR_INVALID, "N = %llu points exceeds 2^30", N);
     if (nz > 65535) return fail(LBM_ERR_INVALID, "nz must be <= 65535 (got %d)", nz);
-    if (!(tau > 0.5f) || !std::isfinite(tau)) return fail(LBM_ERR_INVALID, "tau must be finite and > 0.5 (got %g)", (double)tau);
-    lbm_options opt;
-    if (opt_in) opt = *opt_in;
-    else lbm_options_default(&opt);
     if (opt.storage < 0 || opt.storage > 2) return fail(LBM_ERR_INVALID, "unknown storage %d", opt.storage);
     if (opt.pattern < 0 || opt.pattern > 1) return fail(LBM_ERR_INVALID, "unknown pattern %d", opt.pattern);
+    if (opt.gather_mode < 0 || opt.gather_mode > 2) return fail(LBM_ERR_INVALID, "unknown gather_mode %d", opt.gather_mode);
     int bx = opt.block_x, by = opt.block_y;
     if (bx == 0 && by == 0) default_block(nx, bx, by);
     if (bx <= 0 || by <= 0 || bx * by > 1024) return fail(LBM_ERR_INVALID, "bad block shape %dx%d", bx, by);
@@ -312,6 +389,84 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
         return fail(LBM_ERR_INVALID, "cells_per_lane = %d needs the AB pattern, nx %% %d == 0 and <= 256 work-items per group",
                     vw, vw);
     if (cpl > 1 && (ny + by4 - 1) / by4 > 65535) return fail(LBM_ERR_INVALID, "ny/block_y must be <= 65535 work-groups");
+    lay.bx = bx; lay.by = by; lay.cpl = cpl; lay.bx4 = bx4; lay.by4 = by4; lay.flat = flat;
+    return LBM_OK;
+}
+
+d3q19::Dims dims_of(int nx, int ny, int nz)
+{
+    d3q19::Dims d{};
+    d.nx = nx; d.ny = ny; d.nz = nz;
+    d.nxy = (uint32_t)nx * (uint32_t)ny;
+    d.N = (uint32_t)((size_t)nx * ny * nz);
+    return d;
+}
+
+// Early gather from this fraction of fluid points next to a solid on (FP32
+// sphere duct, 10%: 126.7 -> 114.1 us per step; 256^3 cavity, 2%: 3% slower).
+constexpr double EARLY_GATHER_MIN_NEAR_FRACTION = 0.08;
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_query_buffer_sizes(int nx, int ny, int nz, const lbm_options* opt_in, lbm_buffer_sizes* out)
+{
+    if (!out) return fail(LBM_ERR_INVALID, "out is NULL");
+    lbm_options opt;
+    if (opt_in) opt = *opt_in;
+    else lbm_options_default(&opt);
+    Layout lay;
+    lbm_status st = resolve_layout(nx, ny, nz, opt, lay);
+    if (st != LBM_OK) return st;
+    const d3q19::Dims d = dims_of(nx, ny, nz);
+    size_t nblk = 0;
+    out->population_bytes = round256((size_t)Q * d.N * storage_bytes(opt.storage));
+    out->population_arrays = opt.pattern == LBM_PATTERN_AB ? 2 : 1;
+    out->adjoint_bytes = adjoint_bytes_of(d, opt.cells_per_lane != 1, nblk);
+    out->state_bytes = state_bytes_of(d.N);
+    return LBM_OK;
+}
+
+size_t lbm_trajectory_bytes(int nx, int ny, int nz, int T, int K)
+{
+    if (nx <= 0 || ny <= 0 || nz <= 0 || T < 0 || K <= 0) return 0;
+    const unsigned long long N = (unsigned long long)nx * ny * nz;
+    if (N >= (1ull << 30)) return 0;
+    const size_t nck = T == 0 ? 1 : (size_t)((T + K - 1) / K);
+    const size_t segK = (size_t)std::min(K, std::max(T, 1));
+    return (nck + segK - 1) * round256(state_bytes_of((size_t)N));
+}
+
+lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags_host,
+                         const lbm_options* opt_in, lbm_lattice** out)
+{
+    g_last_error.clear();
+    if (!out) return fail(LBM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    lbm_options opt;
+    if (opt_in) opt = *opt_in;
+    else lbm_options_default(&opt);
+    Layout lay;
+    lbm_status st0 = resolve_layout(nx, ny, nz, opt, lay);
+    if (st0 != LBM_OK) return st0;
+    if (!(tau > 0.5f) || !std::isfinite(tau)) return fail(LBM_ERR_INVALID, "tau must be finite and > 0.5 (got %g)", (double)tau);
+    const unsigned long long N = (unsigned long long)nx * ny * nz;
+    const int nbuf = opt.pattern == LBM_PATTERN_AB ? 2 : 1;
+    const bool caller_f = opt.population_dev[0] || opt.population_dev[1];
+    if (caller_f) {
+        for (int b = 0; b < 2; ++b) {
+            if (b < nbuf && !opt.population_dev[b])
+                return fail(LBM_ERR_INVALID, "population_dev[%d] is NULL (the %s pattern needs %d arrays)", b,
+                            nbuf == 2 ? "AB" : "AA", nbuf);
+            if (b >= nbuf && opt.population_dev[b])
+                return fail(LBM_ERR_INVALID, "population_dev[1] must be NULL for the AA pattern");
+            if (b < nbuf && !aligned256(opt.population_dev[b]))
+                return fail(LBM_ERR_INVALID, "population_dev[%d] must be 256-byte aligned", b);
+        }
+        if (nbuf == 2 && opt.population_dev[0] == opt.population_dev[1])
+            return fail(LBM_ERR_INVALID, "population_dev[0] and [1] must be different buffers");
+    }
     bool onsite = false;
     if (flags_host) {
         for (unsigned long long c = 0; c < N; ++c) {
@@ -330,30 +485,32 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
     lbm_lattice* L = new (std::nothrow) lbm_lattice;
     if (!L) return fail(LBM_ERR_OOM, "host allocation failed");
     L->nx = nx; L->ny = ny; L->nz = nz; L->N = (size_t)N;
-    L->dims.nx = nx; L->dims.ny = ny; L->dims.nz = nz;
-    L->dims.nxy = (uint32_t)nx * (uint32_t)ny;
-    L->dims.N = (uint32_t)N;
+    L->dims = dims_of(nx, ny, nz);
     L->device = dev;
     L->storage = opt.storage;
     L->pattern = opt.pattern;
-    L->bx = bx; L->by = by;
+    L->bx = lay.bx; L->by = lay.by;
     L->stream = static_cast<hipStream_t>(opt.hip_stream);
     L->tau = tau;
     L->timing_cap = opt.timing_capacity;
     L->check_interval = opt.check_interval;
-    L->cpl = cpl;
+    L->cpl = lay.cpl;
     L->vec_ok = opt.cells_per_lane != 1;
     L->onsite = onsite;
-    if (cpl > 1) { L->bx4 = bx4; L->by4 = by4; L->flat = flat; }
+    if (lay.cpl > 1) { L->bx4 = lay.bx4; L->by4 = lay.by4; L->flat = lay.flat; }
 
     lbm_status st = LBM_OK;
     const size_t fbytes = (size_t)Q * L->N * storage_bytes(L->storage);
-    const int nbuf = L->pattern == LBM_PATTERN_AB ? 2 : 1;
-    for (int b = 0; b < nbuf && st == LBM_OK; ++b) st = dalloc(L, &L->d_f[b], fbytes, "populations");
+    if (caller_f) {
+        L->own_f = false;
+        for (int b = 0; b < nbuf; ++b) L->d_f[b] = opt.population_dev[b];
+    } else {
+        for (int b = 0; b < nbuf && st == LBM_OK; ++b) st = dalloc(L, &L->d_f[b], fbytes, "populations");
+    }
     if (st == LBM_OK) st = dalloc(L, &L->d_flags, L->N, "flags");
     if (st == LBM_OK) st = dalloc(L, &L->d_smask, L->N * sizeof(uint32_t), "neighbour masks");
     if (st == LBM_OK) st = dalloc(L, &L->d_mmask, L->N * sizeof(uint32_t), "neighbour masks");
-    if (st == LBM_OK) st = dalloc(L, &L->d_check, sizeof(int), "check flag");
+    if (st == LBM_OK) st = dalloc(L, &L->d_check, 4 * sizeof(int), "check flag and counters");
     uint8_t* d_raw = nullptr;
     if (st == LBM_OK) st = dalloc(L, &d_raw, L->N, "raw flags");
     if (st == LBM_OK) {
@@ -361,13 +518,14 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
                                   : hipMemsetAsync(d_raw, 0, L->N, L->stream);
         st = hip_check(L, e, "flags upload");
     }
-    if (st == LBM_OK) st = hip_check(L, hipMemsetAsync(L->d_check, 0, sizeof(int), L->stream), "check flag clear");
+    if (st == LBM_OK) st = hip_check(L, hipMemsetAsync(L->d_check, 0, 4 * sizeof(int), L->stream), "check flag clear");
     if (st == LBM_OK)
-        st = hip_check(L, lbmk::launch_mark_near_wall(d_raw, L->d_flags, L->d_smask, L->d_mmask, L->d_check, L->dims,
+        st = hip_check(L, lbmk::launch_mark_near_wall(d_raw, L->d_flags, L->d_smask, L->d_mmask, L->d_check,
+                                                      reinterpret_cast<unsigned*>(L->d_check + 1), L->dims,
                                                       launch_of(L)), "mark_near_wall");
-    int bad_onsite = 0;
+    int counts[3] = {0, 0, 0};   // bad on-site node, near-wall fluid points, fluid points
     if (st == LBM_OK)
-        st = hip_check(L, hipMemcpyAsync(&bad_onsite, L->d_check, sizeof(int), hipMemcpyDeviceToHost, L->stream),
+        st = hip_check(L, hipMemcpyAsync(counts, L->d_check, sizeof counts, hipMemcpyDeviceToHost, L->stream),
                        "check flag read");
     // rest state in every array (solid points keep it forever)
     for (int b = 0; b < nbuf && st == LBM_OK; ++b)
@@ -378,7 +536,7 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
             if (st == LBM_OK) st = hip_check(L, hipEventCreate(&ev), "hipEventCreate");
     }
     if (st == LBM_OK) st = hip_check(L, hipStreamSynchronize(L->stream), "create sync");
-    if (st == LBM_OK && bad_onsite)
+    if (st == LBM_OK && counts[0])
         st = fail(LBM_ERR_INVALID, "an on-site velocity node (flag 3 or 4) has solid neighbours that do not form "
                                    "a box face, edge or corner");
     if (d_raw) dfree(L, d_raw, L->N);
@@ -388,6 +546,10 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
         g_last_error = msg;
         return st;
     }
+    const double near_fraction = counts[2] > 0 ? (double)(unsigned)counts[1] / (double)(unsigned)counts[2] : 0.0;
+    const bool early_ok = L->storage == LBM_STORAGE_F32 && L->pattern == LBM_PATTERN_AB && L->cpl > 1 && !L->onsite;
+    L->early = early_ok && (opt.gather_mode == 2 ||
+                            (opt.gather_mode == 0 && near_fraction >= EARLY_GATHER_MIN_NEAR_FRACTION));
     *out = L;
     return LBM_OK;
 }
@@ -398,13 +560,12 @@ void lbm_destroy(lbm_lattice* L)
     DeviceGuard guard(L->device);
     (void)hipStreamSynchronize(L->stream);
     drop_trajectory(L);
-    const size_t sb = (size_t)Q * L->N * sizeof(float);
-    dfree(L, L->d_adj[0], sb);
-    dfree(L, L->d_adj[1], sb);
-    dfree(L, L->d_taupart, L->taupart_n * sizeof(double));
+    drop_adjoint_buffers(L);
     const size_t fbytes = (size_t)Q * L->N * storage_bytes(L->storage);
-    dfree(L, L->d_f[0], fbytes);
-    dfree(L, L->d_f[1], fbytes);
+    if (L->own_f) {
+        dfree(L, L->d_f[0], fbytes);
+        dfree(L, L->d_f[1], fbytes);
+    }
     dfree(L, L->d_flags, L->N);
     dfree(L, L->d_smask, L->N * sizeof(uint32_t));
     dfree(L, L->d_mmask, L->N * sizeof(uint32_t));
@@ -412,6 +573,7 @@ void lbm_destroy(lbm_lattice* L)
     dfree(L, L->d_force, 3 * L->N * sizeof(float));
     for (auto ev : L->events)
         if (ev) (void)hipEventDestroy(ev);
+    if (L->order_ev) (void)hipEventDestroy(L->order_ev);
     delete L;
 }
 
@@ -432,7 +594,53 @@ lbm_status lbm_set_stream(lbm_lattice* L, void* s)
 {
     lbm_status st = usable(L);
     if (st != LBM_OK) return st;
-    L->stream = static_cast<hipStream_t>(s);
+    hipStream_t ns = static_cast<hipStream_t>(s);
+    if (ns == L->stream) return LBM_OK;
+    DeviceGuard guard(L->device);
+    // work already queued on the old stream comes before anything enqueued
+    // on the new one
+    if (!L->order_ev) HIPCHK(L, hipEventCreateWithFlags(&L->order_ev, hipEventDisableTiming));
+    HIPCHK(L, hipEventRecord(L->order_ev, L->stream));
+    HIPCHK(L, hipStreamWaitEvent(ns, L->order_ev, 0));
+    L->stream = ns;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_trajectory_buffer(lbm_lattice* L, void* dev, size_t bytes)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (dev && !aligned256(dev)) return fail(LBM_ERR_INVALID, "trajectory buffer must be 256-byte aligned");
+    DeviceGuard guard(L->device);
+    HIPCHK(L, hipStreamSynchronize(L->stream));   // the old store may still be read
+    drop_trajectory(L);
+    L->traj_dev = dev;
+    L->traj_bytes = dev ? bytes : 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_set_adjoint_buffer(lbm_lattice* L, void* dev, size_t bytes)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    size_t nblk = 0;
+    const size_t need = adjoint_bytes_of(L->dims, L->vec_ok, nblk);
+    if (dev && !aligned256(dev)) return fail(LBM_ERR_INVALID, "adjoint buffer must be 256-byte aligned");
+    if (dev && bytes < need)
+        return fail(LBM_ERR_INVALID, "adjoint buffer of %zu bytes is smaller than the %zu bytes needed", bytes, need);
+    DeviceGuard guard(L->device);
+    HIPCHK(L, hipStreamSynchronize(L->stream));
+    drop_adjoint_buffers(L);
+    L->adj_dev = dev;
+    L->adj_bytes = dev ? bytes : 0;
+    if (dev) {
+        const size_t sbr = round256(state_bytes_of(L->N));
+        char* base = static_cast<char*>(dev);
+        L->d_adj[0] = reinterpret_cast<float*>(base);
+        L->d_adj[1] = reinterpret_cast<float*>(base + sbr);
+        L->d_taupart = reinterpret_cast<double*>(base + 2 * sbr);
+        L->taupart_n = nblk;
+    }
     return LBM_OK;
 }
 
@@ -637,21 +845,39 @@ lbm_status lbm_forward_checkpointed(lbm_lattice* L, int T, int K)
     if (L->storage != LBM_STORAGE_F32 || L->pattern != LBM_PATTERN_AB)
         return fail(LBM_ERR_STATE, "the adjoint rollout needs F32 storage and the AB pattern");
     if (L->onsite) return fail(LBM_ERR_STATE, "the adjoint does not cover on-site velocity nodes");
+    const size_t need = lbm_trajectory_bytes(L->nx, L->ny, L->nz, T, K);
+    if (L->traj_dev && need > L->traj_bytes)
+        return fail(LBM_ERR_INVALID, "the trajectory buffer holds %zu bytes; T = %d, K = %d needs %zu", L->traj_bytes,
+                    T, K, need);
     DeviceGuard guard(L->device);
     drop_trajectory(L);
     const size_t sb = (size_t)Q * L->N * sizeof(float);
     const int nck = T == 0 ? 1 : (T + K - 1) / K;
-    for (int k = 0; k < nck; ++k) {
-        float* p = nullptr;
-        st = dalloc(L, &p, sb, "checkpoint");
-        if (st != LBM_OK) { drop_trajectory(L); return st; }
-        L->ckpt.push_back(p);
-    }
     const int segK = std::min(K, std::max(T, 1));
-    if (segK > 1) {
-        st = dalloc(L, &L->d_seg, sb * (size_t)(segK - 1), "segment store");
-        if (st != LBM_OK) { drop_trajectory(L); return st; }
-        L->seg_cap = segK - 1;
+    if (L->traj_dev) {
+        // caller store: checkpoints at 256-byte-aligned state slots, then the
+        // segment states back to back
+        L->traj_owned = false;
+        char* base = static_cast<char*>(L->traj_dev);
+        const size_t sbr = round256(sb);
+        for (int k = 0; k < nck; ++k) L->ckpt.push_back(reinterpret_cast<float*>(base + (size_t)k * sbr));
+        if (segK > 1) {
+            L->d_seg = reinterpret_cast<float*>(base + (size_t)nck * sbr);
+            L->seg_cap = segK - 1;
+        }
+    } else {
+        L->traj_owned = true;
+        for (int k = 0; k < nck; ++k) {
+            float* p = nullptr;
+            st = dalloc(L, &p, sb, "checkpoint");
+            if (st != LBM_OK) { drop_trajectory(L); return st; }
+            L->ckpt.push_back(p);
+        }
+        if (segK > 1) {
+            st = dalloc(L, &L->d_seg, sb * (size_t)(segK - 1), "segment store");
+            if (st != LBM_OK) { drop_trajectory(L); return st; }
+            L->seg_cap = segK - 1;
+        }
     }
     for (int k = 0; k < nck; ++k) {
         HIPCHK(L, hipMemcpyAsync(L->ckpt[k], L->d_f[L->cur], sb, hipMemcpyDeviceToDevice, L->stream));
@@ -676,36 +902,25 @@ lbm_status lbm_adjoint(lbm_lattice* L, const float* g, float* gF, double* grad_t
         return fail(LBM_ERR_STATE, "no valid trajectory: call lbm_forward_checkpointed after the last change");
     DeviceGuard guard(L->device);
     const size_t sb = (size_t)Q * L->N * sizeof(float);
-    for (int b = 0; b < 2; ++b)
-        if (!L->d_adj[b]) {
-            st = dalloc(L, &L->d_adj[b], sb, "adjoint buffer");
-            if (st != LBM_OK) return st;
-        }
-    const lbmk::Launch LA = launch_of(L);
-    // Reverse step: two x-points per work-item with 64-work-item groups (the
-    // fastest shape measured at 256^3; four points need too many registers),
-    // else one point per work-item with at most 256 work-items per group.
-    const bool vec = L->vec_ok && L->nx % 2 == 0;
-    lbmk::Launch LR;
-    if (vec) {
-        d3q19::Dims q = L->dims;
-        q.nx = L->nx / 2;
-        const int rbx = std::min(q.nx, 64);
-        LR = lbmk::make_launch(q, rbx, std::max(1, 64 / rbx), L->stream);
-    } else {
-        int abx, aby;
-        default_block(L->nx, abx, aby);
-        LR = lbmk::make_launch(L->dims, abx, aby, L->stream);
-    }
+    bool vec = false;
+    const lbmk::Launch LR = adjoint_launch(L->dims, L->vec_ok, L->stream, vec);
     const size_t nblk = (size_t)LR.grid.x * LR.grid.y * LR.grid.z;
-    if (L->taupart_n < nblk) {
-        dfree(L, L->d_taupart, L->taupart_n * sizeof(double));
-        L->d_taupart = nullptr;
-        L->taupart_n = 0;
-        st = dalloc(L, &L->d_taupart, nblk * sizeof(double), "tau partials");
-        if (st != LBM_OK) return st;
-        L->taupart_n = nblk;
+    if (!L->adj_dev) {
+        for (int b = 0; b < 2; ++b)
+            if (!L->d_adj[b]) {
+                st = dalloc(L, &L->d_adj[b], sb, "adjoint buffer");
+                if (st != LBM_OK) return st;
+            }
+        if (L->taupart_n < nblk) {
+            dfree(L, L->d_taupart, L->taupart_n * sizeof(double));
+            L->d_taupart = nullptr;
+            L->taupart_n = 0;
+            st = dalloc(L, &L->d_taupart, nblk * sizeof(double), "tau partials");
+            if (st != LBM_OK) return st;
+            L->taupart_n = nblk;
+        }
     }
+    const lbmk::Launch LA = launch_of(L);
     HIPCHK(L, hipMemsetAsync(L->d_taupart, 0, nblk * sizeof(double), L->stream));
 
     const lbmk::StepArgs args = step_args(L);

@@ -31,8 +31,11 @@ class Lattice:
     pattern: 'ab' (two arrays) | 'aa' (one array, in place).
     """
 
+    GATHER_MODES = {"auto": 0, "flags_first": 1, "early": 2}
+
     def __init__(self, nx, ny, nz, tau, flags=None, storage="f32", pattern="ab", block=None,
-                 timing=0, check_interval=0, device=None, stream=None, cells_per_lane=0):
+                 timing=0, check_interval=0, device=None, stream=None, cells_per_lane=0,
+                 gather_mode="auto", torch_buffers=False):
         if not torch.cuda.is_available():
             raise RuntimeError("Lattice needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -53,6 +56,20 @@ class Lattice:
         opt.check_interval = int(check_interval)
         opt.device = self.device.index
         opt.cells_per_lane = int(cells_per_lane)
+        opt.gather_mode = self.GATHER_MODES[gather_mode]
+        # torch_buffers: the population arrays, the adjoint workspace and the
+        # checkpoint store are torch allocations handed to the library
+        self.torch_buffers = bool(torch_buffers)
+        self._bufs = {}
+        if self.torch_buffers:
+            sizes = _abi.lbm_buffer_sizes()
+            _abi.call("lbm_query_buffer_sizes", self.nx, self.ny, self.nz, ctypes.byref(opt),
+                      ctypes.byref(sizes))
+            self._sizes = sizes
+            pops = [self._device_buffer(sizes.population_bytes) for _ in range(sizes.population_arrays)]
+            self._bufs["populations"] = pops
+            for b, t in enumerate(pops):
+                opt.population_dev[b] = t.data_ptr()
         fl = None
         if flags is not None:
             fl = np.ascontiguousarray(
@@ -66,6 +83,17 @@ class Lattice:
                   ctypes.byref(opt), ctypes.byref(h))
         self._h = h
         self.tau = float(np.float32(tau))
+        if self.torch_buffers and storage == "f32" and pattern == "ab":
+            adj = self._device_buffer(self._sizes.adjoint_bytes)
+            _abi.call("lbm_set_adjoint_buffer", self._h, _ptr(adj), ctypes.c_size_t(adj.numel()))
+            self._bufs["adjoint"] = adj
+
+    def _device_buffer(self, nbytes):
+        """A torch byte buffer on the lattice's device, 256-byte aligned."""
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        if t.data_ptr() % 256:
+            raise RuntimeError("torch returned a buffer that is not 256-byte aligned")
+        return t
 
     # -- lifetime -----------------------------------------------------------
     def close(self):
@@ -170,6 +198,15 @@ class Lattice:
 
     # -- adjoint ------------------------------------------------------------
     def forward_checkpointed(self, T, K):
+        if self.torch_buffers:
+            need = int(_abi.lib().lbm_trajectory_bytes(self.nx, self.ny, self.nz, int(T), int(K)))
+            cur = self._bufs.get("trajectory")
+            if cur is None or cur.numel() < need:
+                # the library stops using the old buffer before returning
+                self._bufs["trajectory"] = None
+                traj = self._device_buffer(max(need, 256))
+                _abi.call("lbm_set_trajectory_buffer", self._h, _ptr(traj), ctypes.c_size_t(traj.numel()))
+                self._bufs["trajectory"] = traj
         _abi.call("lbm_forward_checkpointed", self._h, int(T), int(K))
 
     def adjoint(self, dL_du):

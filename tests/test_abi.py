@@ -106,6 +106,60 @@ def test_create_rejects_bad_flags_and_options(abi):
     assert st == abi.LBM_ERR_INVALID
 
 
+def test_create_rejects_bad_modes_and_caller_buffers(abi):
+    """Caller-owned population arrays and the launch-mode options are
+    validated before any HIP call."""
+    def opt_with(**kw):
+        opt = abi.lbm_options()
+        abi.lib().lbm_options_default(ctypes.byref(opt))
+        for k, v in kw.items():
+            if k == "population_dev":
+                opt.population_dev[0], opt.population_dev[1] = v
+            else:
+                setattr(opt, k, v)
+        return opt
+    cases = [
+        (dict(gather_mode=-1), "gather_mode"),
+        (dict(population_dev=(4096, None)), "population_dev[1] is NULL"),
+        (dict(population_dev=(4096 + 64, 8192)), "256-byte aligned"),
+        (dict(population_dev=(4096, 4096)), "different"),
+        (dict(pattern=1, population_dev=(4096, 8192)), "must be NULL for the AA"),
+    ]
+    for kw, msg in cases:
+        st, h = _create(abi, 8, 8, 8, 0.8, None, opt_with(**kw))
+        assert st == abi.LBM_ERR_INVALID and not h.value, kw
+        assert msg in abi.last_error(), (kw, abi.last_error())
+
+
+def test_buffer_size_queries(abi):
+    """Sizes a caller needs to allocate the library's buffers itself:
+    19 populations per point in 4 or 2 bytes, two arrays for AB and one for
+    AA; the adjoint workspace holds two FP32 states; the checkpoint store
+    ceil(T/K) + min(K, T) - 1 states."""
+    L = abi.lib()
+    out = abi.lbm_buffer_sizes()
+    nx, ny, nz = 36, 10, 9
+    N = nx * ny * nz
+    assert L.lbm_query_buffer_sizes(nx, ny, nz, None, ctypes.byref(out)) == abi.LBM_OK
+    r256 = lambda b: (b + 255) // 256 * 256
+    assert out.population_bytes == r256(19 * N * 4) and out.population_arrays == 2
+    assert out.state_bytes == 19 * N * 4
+    assert out.adjoint_bytes >= 2 * r256(19 * N * 4) + 8
+    opt = abi.lbm_options()
+    L.lbm_options_default(ctypes.byref(opt))
+    opt.storage, opt.pattern = abi.STORAGE["f16"], abi.PATTERN["aa"]
+    assert L.lbm_query_buffer_sizes(nx, ny, nz, ctypes.byref(opt), ctypes.byref(out)) == abi.LBM_OK
+    assert out.population_bytes == r256(19 * N * 2) and out.population_arrays == 1
+    assert L.lbm_query_buffer_sizes(0, ny, nz, None, ctypes.byref(out)) == abi.LBM_ERR_INVALID
+    assert L.lbm_query_buffer_sizes(nx, ny, nz, None, None) == abi.LBM_ERR_INVALID
+    sb = r256(19 * N * 4)
+    assert L.lbm_trajectory_bytes(nx, ny, nz, 200, 20) == (10 + 19) * sb
+    assert L.lbm_trajectory_bytes(nx, ny, nz, 12, 5) == (3 + 4) * sb
+    assert L.lbm_trajectory_bytes(nx, ny, nz, 0, 5) == 1 * sb
+    assert L.lbm_trajectory_bytes(nx, ny, nz, 3, 10) == (1 + 2) * sb
+    assert L.lbm_trajectory_bytes(nx, ny, nz, 5, 0) == 0
+
+
 def test_calls_on_null_lattice(abi):
     L = abi.lib()
     assert L.lbm_step(None, 1) == abi.LBM_ERR_INVALID
@@ -115,6 +169,9 @@ def test_calls_on_null_lattice(abi):
     gt = ctypes.c_double()
     assert L.lbm_adjoint(None, None, None, ctypes.byref(gt)) == abi.LBM_ERR_INVALID
     assert L.lbm_device_bytes(None) == 0
+    assert L.lbm_set_trajectory_buffer(None, None, 0) == abi.LBM_ERR_INVALID
+    assert L.lbm_set_adjoint_buffer(None, None, 0) == abi.LBM_ERR_INVALID
+    assert L.lbm_set_stream(None, None) == abi.LBM_ERR_INVALID
     L.lbm_destroy(None)  # no-op
 
 

@@ -1,0 +1,165 @@
+"""Launch modes and caller-owned memory change nothing in the results.
+
+- the gather modes (flags first / early gather) of the multi-point AB step
+  give bit-identical states;
+- populations, the checkpoint store and the adjoint workspace may be
+  torch allocations handed to the library: states, macroscopic fields and
+  adjoint gradients are bit-identical to library-allocated runs, and
+  lbm_device_bytes does not count the caller's buffers;
+- switching the launch stream between calls keeps the work in order.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests.gpu_common import near_rest_state
+
+pytestmark = pytest.mark.gpu
+Q = 19
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1309_1983_amd
+    paper_1309_1983_amd.lib()
+
+
+def _run(shape, tau, flags, s0, steps, uw=(0.05, -0.02, 0.03), ff=None, force=None, **kw):
+    from paper_1309_1983_amd import Lattice
+    lat = Lattice(*shape, tau, flags=flags, **kw)
+    lat.set_wall_velocity(*uw)
+    if ff is not None:
+        lat.set_force(torch.from_numpy(ff))
+    if force is not None:
+        lat.set_force(force)
+    lat.set_populations(torch.from_numpy(s0))
+    lat.step(steps)
+    out = lat.populations().cpu().numpy()
+    rho, u = (t.cpu().numpy() for t in lat.macros())
+    lat.close()
+    return out, rho, u
+
+
+MODE_CASES = [
+    # shape, solid fraction, moving fraction, per-point force
+    ((36, 17, 11), 0.2, 0.05, True),
+    ((64, 9, 7), 0.0, 0.0, False),
+    ((260, 5, 3), 0.2, 0.05, True),    # one-dimensional grid
+]
+
+
+@pytest.mark.parametrize("case", range(len(MODE_CASES)))
+def test_gather_modes_are_bitwise_equal_f32(case):
+    shape, solid, moving, field = MODE_CASES[case]
+    N = int(np.prod(shape))
+    flags = W.random_flags(N, seed=60 + case, solid_fraction=solid, moving_fraction=moving)
+    ff = W.random_force_field(N, 61, 1e-4).astype(np.float32) if field else None
+    s0 = near_rest_state(N, 62 + case)
+    ref = _run(shape, 0.8, flags, s0, 5, ff=ff, cells_per_lane=1)
+    fl = flags == 0
+    for gm in ("flags_first", "early", "auto"):
+        got = _run(shape, 0.8, flags, s0, 5, ff=ff, gather_mode=gm)
+        np.testing.assert_array_equal(got[0][:, fl], ref[0][:, fl], err_msg=gm)
+        np.testing.assert_array_equal(got[1], ref[1])
+        np.testing.assert_array_equal(got[2], ref[2])
+
+
+def test_porous_geometry_takes_early_gather_and_matches_one_point_kernel():
+    """The sphere duct (about 10% of its fluid points next to a solid) is run
+    with the early gather by default; the state equals the one-point
+    kernel's bit for bit."""
+    shape = (48, 40, 64)
+    flags = W.sphere_duct_flags(*shape, seed=5, solid_fraction=0.10)
+    s0 = near_rest_state(flags.size, 12, 0.005, 0.01)
+    ref = _run(shape, 0.7, flags, s0, 6, uw=(0, 0, 0), force=(0, 0, 1e-6), cells_per_lane=1)
+    fl = flags == 0
+    for gm in ("auto", "early", "flags_first"):
+        got = _run(shape, 0.7, flags, s0, 6, uw=(0, 0, 0), force=(0, 0, 1e-6), gather_mode=gm)
+        np.testing.assert_array_equal(got[0][:, fl], ref[0][:, fl], err_msg=gm)
+
+
+@pytest.mark.parametrize("storage,pattern", [("f32", "ab"), ("f16", "aa"), ("bf16", "ab")])
+def test_torch_owned_populations_are_bitwise_equal(storage, pattern):
+    from paper_1309_1983_amd import Lattice
+    shape = (36, 17, 11)
+    N = int(np.prod(shape))
+    flags = W.random_flags(N, seed=80, solid_fraction=0.2, moving_fraction=0.05)
+    ff = W.random_force_field(N, 81, 1e-4).astype(np.float32)
+    s0 = near_rest_state(N, 82)
+    ref = _run(shape, 0.8, flags, s0, 7, ff=ff, storage=storage, pattern=pattern)
+    got = _run(shape, 0.8, flags, s0, 7, ff=ff, storage=storage, pattern=pattern, torch_buffers=True)
+    for a, b in zip(got, ref):
+        np.testing.assert_array_equal(a, b)
+    own = Lattice(*shape, 0.8, flags=flags, storage=storage, pattern=pattern)
+    ext = Lattice(*shape, 0.8, flags=flags, storage=storage, pattern=pattern, torch_buffers=True)
+    pop = 19 * N * (4 if storage == "f32" else 2) * ext._sizes.population_arrays
+    assert own.device_bytes() - ext.device_bytes() == pop
+    own.close()
+    ext.close()
+
+
+def test_torch_owned_trajectory_and_adjoint_buffers():
+    from paper_1309_1983_amd import LBMError, Lattice
+    shape, tau, T, K = (36, 10, 9), 0.7, 11, 4
+    flags = W.duct_flags(*shape)
+    N = flags.size
+    F = torch.from_numpy(W.random_force_field(N, 3, 1e-3).astype(np.float32))
+    s0 = torch.from_numpy(near_rest_state(N, 4))
+    g = torch.from_numpy(W.random_velocity(N, 5, 1.0).astype(np.float32))
+    out = []
+    for tb in (False, True):
+        lat = Lattice(*shape, tau, flags=flags, torch_buffers=tb)
+        lat.set_wall_velocity(0.02, 0.0, 0.01)
+        lat.set_force(F)
+        lat.set_populations(s0)
+        lat.forward_checkpointed(T, K)
+        gF, gt = lat.adjoint(g)
+        out.append((gF.cpu(), gt, lat.device_bytes(), lat))
+    assert torch.equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+    # the library holds the trajectory and adjoint buffers itself only in the first run
+    state = 19 * N * 4
+    traj_states = (T + K - 1) // K + K - 1
+    assert out[0][2] - out[1][2] >= (traj_states + 2) * state + 2 * 19 * N * 4
+    lat = out[1][3]
+    # a caller store too small for a longer rollout is refused, not replaced
+    from paper_1309_1983_amd import _abi
+    import ctypes
+    small = torch.empty(4 * state, dtype=torch.uint8, device="cuda")
+    _abi.call("lbm_set_trajectory_buffer", lat._h, ctypes.c_void_p(small.data_ptr()), ctypes.c_size_t(small.numel()))
+    lat._bufs["trajectory"] = small
+    with pytest.raises(LBMError, match="INVALID"):
+        _abi.call("lbm_forward_checkpointed", lat._h, 40, 20)
+    with pytest.raises(LBMError, match="INVALID"):
+        _abi.call("lbm_set_adjoint_buffer", lat._h, ctypes.c_void_p(small.data_ptr()), ctypes.c_size_t(1024))
+    for o in out:
+        o[3].close()
+
+
+def test_stream_switches_keep_order():
+    """Alternating the launch stream between calls (torch side streams) gives
+    the single-stream result bit for bit: each switch orders the new stream
+    after the work queued on the old one."""
+    from paper_1309_1983_amd import Lattice
+    shape = (128, 64, 48)
+    flags = W.cavity_flags(*shape)
+    s0 = torch.from_numpy(near_rest_state(flags.size, 90))
+    ref_lat = Lattice(*shape, 0.6, flags=flags)
+    ref_lat.set_wall_velocity(0.1)
+    ref_lat.set_populations(s0)
+    ref_lat.step(40)
+    ref = ref_lat.populations().cpu()
+    ref_lat.close()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.current_stream()]
+    lat = Lattice(*shape, 0.6, flags=flags)
+    lat.set_wall_velocity(0.1)
+    lat.set_populations(s0)
+    for k in range(40):
+        lat.set_stream(streams[k % 3])
+        lat.step(1)
+    lat.set_stream(torch.cuda.current_stream())
+    got = lat.populations().cpu()
+    lat.close()
+    fl = torch.from_numpy(flags == 0)
+    assert torch.equal(got[:, fl], ref[:, fl])
