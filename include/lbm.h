@@ -285,6 +285,24 @@ lbm_status lbm_forward_checkpointed(lbm_lattice* lat, int T, int K);
 lbm_status lbm_adjoint(lbm_lattice* lat, const float* dL_du_dev, float* grad_F_dev,
                        double* grad_tau_host);
 
+/*
+ * The same reverse sweep as lbm_adjoint, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): it calls no allocating routine. Its two
+ * adjoint arrays, per-work-group dL/dtau partials and their sum live in one
+ * static device array of the library (40 MiB per GPU, held until the process
+ * ends), so the lattice may have at most 2^18 points (e.g. 64^3); larger
+ * lattices get LBM_ERR_INVALID and use lbm_adjoint. The trajectory must come
+ * from lbm_forward_checkpointed (its store allocated then, or given with
+ * lbm_set_trajectory_buffer). Results are bit-identical to lbm_adjoint
+ * (dL/dtau is summed in the same order). Every call on one GPU shares that
+ * array: calls that overlap on the same GPU (two streams, two threads) race
+ * and give wrong results. Synchronises the stream before returning.
+ * Errors: as lbm_adjoint; LBM_ERR_INVALID for more than 2^18 points.
+ */
+lbm_status lbm_adjoint_noalloc(lbm_lattice* lat, const float* dL_du_dev, float* grad_F_dev,
+                               double* grad_tau_host);
+
 /* Checks every stored population of the fluid points for NaN/Inf.
  * Synchronises. Returns LBM_OK or LBM_ERR_NONFINITE. */
 lbm_status lbm_check_finite(lbm_lattice* lat);

@@ -21,7 +21,7 @@ EXPORTS = [
     "lbm_set_stream", "lbm_set_tau", "lbm_set_wall_velocity", "lbm_set_force_uniform",
     "lbm_set_force_field", "lbm_init_equilibrium", "lbm_step", "lbm_step_macros", "lbm_macros",
     "lbm_get_populations", "lbm_set_populations", "lbm_debug_stream_only",
-    "lbm_forward_checkpointed", "lbm_adjoint", "lbm_check_finite", "lbm_step_times", "lbm_sync",
+    "lbm_forward_checkpointed", "lbm_adjoint", "lbm_adjoint_noalloc", "lbm_check_finite", "lbm_step_times", "lbm_sync",
     "lbm_device_bytes", "lbm_status_string", "lbm_last_error", "lbm_copy_f32",
 ]
 # include/lbm_study.h
@@ -104,6 +104,7 @@ def lib():
         "lbm_debug_stream_only": (c_int, [vp, c_int]),
         "lbm_forward_checkpointed": (c_int, [vp, c_int, c_int]),
         "lbm_adjoint": (c_int, [vp, fp, fp, dp]),
+        "lbm_adjoint_noalloc": (c_int, [vp, fp, fp, dp]),
         "lbm_check_finite": (c_int, [vp]),
         "lbm_step_times": (c_int, [vp, ctypes.POINTER(c_float), c_int, ip]),
         "lbm_sync": (c_int, [vp]),

@@ -107,4 +107,9 @@ hipError_t launch_adjoint_stepv(int vw, bool direct, int force_mode, const float
                                 const uint32_t* smask, const uint32_t* mmask, const float* ffield,
                                 const StepArgs& args, float inv_tau2, const Launch& L);
 
+// p[0..n) = 0 (a kernel, not a memset). out[0] = sum of p[0..n) added in
+// index order by one work-item.
+hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s);
+hipError_t launch_sum_f64_ordered(const double* p, size_t n, double* out, hipStream_t s);
+
 }  // namespace lbmk

@@ -343,6 +343,38 @@ __global__ __launch_bounds__(256, 3) void k_adj_stepv(const float* __restrict__ 
     block_tau_sum(tsum, taupart);
 }
 
+// Zero n doubles with a kernel (no memset node, so the launch may be captured).
+__global__ __launch_bounds__(256) void k_zero_f64(double* __restrict__ p, size_t n)
+{
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0.0;
+}
+
+// out[0] = p[0] + p[1] + ... + p[n-1], added one by one in index order by a
+// single work-item: the order and rounding of the host loop that sums the
+// per-work-group tau partials, so both give the same bits.
+__global__ __launch_bounds__(64) void k_sum_f64_ordered(const double* __restrict__ p, size_t n,
+                                                        double* __restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (size_t k = 0; k < n; ++k) s += p[k];
+    out[0] = s;
+}
+
+hipError_t launch_zero_f64(double* p, size_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_f64_ordered(const double* p, size_t n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_f64_ordered, dim3(1), dim3(64), 0, s, p, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_adjoint_seed(int fm, const float* f, const uint8_t* flags, const float* ff,
                                const float* g, float* aout, float* gF, const StepArgs& args,
                                const Launch& L)

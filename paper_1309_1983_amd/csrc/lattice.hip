@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -296,6 +297,8 @@ void drop_adjoint_buffers(lbm_lattice* L)
 void invalidate(lbm_lattice* L) { ++L->version; }
 
 lbm_status run_steps(lbm_lattice* L, int n, bool collide, float* rho = nullptr, float* u = nullptr);
+lbm_status adjoint_sweep(lbm_lattice* L, const float* g, float* gF, float* adj[2], double* part,
+                         const lbmk::Launch& LR, bool vec);
 
 }  // namespace
 
@@ -920,9 +923,116 @@ lbm_status lbm_adjoint(lbm_lattice* L, const float* g, float* gF, double* grad_t
             L->taupart_n = nblk;
         }
     }
-    const lbmk::Launch LA = launch_of(L);
     HIPCHK(L, hipMemsetAsync(L->d_taupart, 0, nblk * sizeof(double), L->stream));
+    float* adj[2] = {L->d_adj[0], L->d_adj[1]};
+    st = adjoint_sweep(L, g, gF, adj, L->d_taupart, LR, vec);
+    if (st != LBM_OK) return st;
+    std::vector<double> parts(nblk);
+    HIPCHK(L, hipMemcpyAsync(parts.data(), L->d_taupart, nblk * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(L, hipStreamSynchronize(L->stream));
+    double s = 0.0;
+    for (double v : parts) s += v;
+    *grad_tau = s;
+    return LBM_OK;
+}
 
+}  // extern "C"
+
+// ------------------------- allocation-free adjoint -------------------------
+// lbm_adjoint_noalloc keeps its adjoint arrays, tau partials and tau sum in
+// `scratch`, a file-scope device array that every GPU the library runs on
+// holds for the life of the process. In host code the array's name is only a
+// stand-in: its device address comes from hipGetSymbolAddress, once per
+// device with that device current, and only that address is handed to
+// kernels. Calls on one GPU share the array: overlapping calls race.
+namespace {
+
+constexpr size_t NOALLOC_MAX_POINTS = (size_t)1 << 18;   // a 64^3 lattice
+constexpr size_t NOALLOC_STATE_BYTES = ((size_t)Q * NOALLOC_MAX_POINTS * sizeof(float) + 255) & ~(size_t)255;
+constexpr size_t NOALLOC_PART_OFFSET = 2 * NOALLOC_STATE_BYTES;
+constexpr size_t NOALLOC_SUM_OFFSET = NOALLOC_PART_OFFSET + NOALLOC_MAX_POINTS * sizeof(double);
+constexpr size_t NOALLOC_SCRATCH_BYTES = NOALLOC_SUM_OFFSET + 256;   // 38.0 MiB + 2 MiB + 256 B
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on device `dev` (current), looked up on the
+// first call for that device.
+lbm_status scratch_on(int dev, char** out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(LBM_ERR_DEVICE, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(LBM_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = static_cast<char*>(g_scratch_ptr[dev]);
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbm_status lbm_adjoint_noalloc(lbm_lattice* L, const float* g, float* gF, double* grad_tau)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (!g || !gF || !grad_tau) return fail(LBM_ERR_INVALID, "NULL argument");
+    if (L->N > NOALLOC_MAX_POINTS)
+        return fail(LBM_ERR_INVALID, "lbm_adjoint_noalloc handles at most %zu points (a 64^3 lattice); this lattice "
+                                     "has %zu: use lbm_adjoint", NOALLOC_MAX_POINTS, L->N);
+    if (L->traj_T < 0 || L->traj_version != L->version)
+        return fail(LBM_ERR_STATE, "no valid trajectory: call lbm_forward_checkpointed after the last change");
+    DeviceGuard guard(L->device);
+    bool vec = false;
+    const lbmk::Launch LR = adjoint_launch(L->dims, L->vec_ok, L->stream, vec);
+    const size_t nblk = (size_t)LR.grid.x * LR.grid.y * LR.grid.z;
+    if (nblk > NOALLOC_MAX_POINTS)   // at most one work-group per point
+        return fail(LBM_ERR_INVALID, "%zu reverse-step work-groups exceed the scratch partials", nblk);
+    char* base = nullptr;
+    st = scratch_on(L->device, &base);
+    if (st != LBM_OK) {
+        L->sticky = true;
+        return st;
+    }
+    float* adj[2] = {reinterpret_cast<float*>(base), reinterpret_cast<float*>(base + NOALLOC_STATE_BYTES)};
+    double* part = reinterpret_cast<double*>(base + NOALLOC_PART_OFFSET);
+    double* sum = reinterpret_cast<double*>(base + NOALLOC_SUM_OFFSET);
+    // the partials accumulate over the reverse steps: clear this call's
+    // (the previous call's contents stay in the array)
+    HIPCHK(L, lbmk::launch_zero_f64(part, nblk, L->stream));
+    st = adjoint_sweep(L, g, gF, adj, part, LR, vec);
+    if (st != LBM_OK) return st;
+    HIPCHK(L, lbmk::launch_sum_f64_ordered(part, nblk, sum, L->stream));
+    double h = 0.0;
+    HIPCHK(L, hipMemcpyAsync(&h, sum, sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(L, hipStreamSynchronize(L->stream));
+    *grad_tau = h;
+    return LBM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Seed plus reverse sweep over the recorded trajectory: adjoint arrays adj[0]
+// and adj[1] (19 N floats each), tau partials `part` (one per reverse-step
+// work-group, zeroed by the caller), reverse-step launch LR.
+lbm_status adjoint_sweep(lbm_lattice* L, const float* g, float* gF, float* adj[2], double* part,
+                         const lbmk::Launch& LR, bool vec)
+{
+    const lbmk::Launch LA = launch_of(L);
     const lbmk::StepArgs args = step_args(L);
     const int fm = force_mode(L);
     const float inv_tau2 = (float)(1.0 / ((double)L->tau * (double)L->tau));
@@ -931,8 +1041,8 @@ lbm_status lbm_adjoint(lbm_lattice* L, const float* g, float* gF, double* grad_t
 
     // seed from the final state (the lattice's current array)
     HIPCHK(L, lbmk::launch_adjoint_seed(fm, static_cast<const float*>(L->d_f[L->cur]), L->d_flags, L->d_force, g,
-                                        L->d_adj[0], gF, args, LA));
-    int ab = 0;            // d_adj[ab] holds the adjoint input of the next reverse step
+                                        adj[0], gF, args, LA));
+    int ab = 0;            // adj[ab] holds the adjoint input of the next reverse step
     bool direct = true;
     for (int k = nck - 1; k >= 0 && T > 0; --k) {
         const int t0 = k * K;
@@ -949,28 +1059,18 @@ lbm_status lbm_adjoint(lbm_lattice* L, const float* g, float* gF, double* grad_t
         }
         for (int j = len - 1; j >= 0; --j) {
             if (vec)
-                HIPCHK(L, lbmk::launch_adjoint_stepv(2, direct, fm, state(j), L->d_adj[ab], L->d_adj[ab ^ 1], gF,
-                                                     L->d_taupart, L->d_flags, L->d_smask, L->d_mmask, L->d_force,
-                                                     args, inv_tau2, LR));
+                HIPCHK(L, lbmk::launch_adjoint_stepv(2, direct, fm, state(j), adj[ab], adj[ab ^ 1], gF, part,
+                                                     L->d_flags, L->d_smask, L->d_mmask, L->d_force, args, inv_tau2,
+                                                     LR));
             else
-                HIPCHK(L, lbmk::launch_adjoint_step(direct, fm, state(j), L->d_adj[ab], L->d_adj[ab ^ 1], gF,
-                                                    L->d_taupart, L->d_flags, L->d_force, args, inv_tau2, LR));
+                HIPCHK(L, lbmk::launch_adjoint_step(direct, fm, state(j), adj[ab], adj[ab ^ 1], gF, part, L->d_flags,
+                                                    L->d_force, args, inv_tau2, LR));
             ab ^= 1;
             direct = false;
         }
     }
-    std::vector<double> parts(nblk);
-    HIPCHK(L, hipMemcpyAsync(parts.data(), L->d_taupart, nblk * sizeof(double), hipMemcpyDeviceToHost, L->stream));
-    HIPCHK(L, hipStreamSynchronize(L->stream));
-    double s = 0.0;
-    for (double v : parts) s += v;
-    *grad_tau = s;
     return LBM_OK;
 }
-
-}  // extern "C"
-
-namespace {
 
 // n steps; with rho/u (AB pattern) the last step also stores its in-step
 // rho and u.
