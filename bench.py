@@ -12,8 +12,11 @@ Printed JSON line (rank 0, stdout): the contract fields, plus
                 over its average duration, vs the 8 TB/s MI355X peak;
   cpu_baseline  the FP64 oracle timed on the host cores on a bounded sample;
   extra         16-bit offset storage (two-array and in-place AA) rates, the
-                adjoint reverse sweep rate, the measured copy ceiling, and the
-                per-step time distribution with its periodogram peak.
+                adjoint reverse sweep rates (256^3 and 64^3), the measured
+                copy ceiling, the access pattern's own ceilings (the step
+                without collision; its 19-plane streams without shifts), the
+                other workload configurations, and the per-step time
+                distribution with its periodogram peak.
 Progress goes to stderr.
 """
 from __future__ import annotations
@@ -34,7 +37,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, decimal GB/s
 BYTES_PER_POINT = {"f32": 152, "f16": 76, "bf16": 76}   # 19 loads + 19 stores
 MACROS_BYTES = 16   # rho and u stored every step (Section 4.1: 152 -> 168 B)
-ADJOINT_BYTES_PER_POINT = 152 + 264  # recompute step + reverse step (see DESIGN)
+FORCE_FIELD_BYTES = 12   # a per-point force [3][N] FP32 read by every step
+# reverse step: reads b 76, s 76 and F 12; writes b 76; grad_F read and written 24
+ADJOINT_REVERSE_BYTES = 264
+# per point and time step of the reverse sweep: the recompute step with the
+# force field (152 + 12) plus the reverse step
+ADJOINT_BYTES_PER_POINT = BYTES_PER_POINT["f32"] + FORCE_FIELD_BYTES + ADJOINT_REVERSE_BYTES
 
 
 def log(msg):
@@ -62,15 +70,19 @@ def load_traffic(workload):
     return d.get("hbm_bytes_per_launch")
 
 
-def time_steps(lat, steps, torch):
+def time_steps(lat, steps, torch, stream_only=False):
     """Average ms per step over `steps` back-to-back launches, with HIP events
-    recorded on the lattice's stream."""
+    recorded on the lattice's stream (the stream the kernels run on).
+    stream_only: the streaming half alone (no collision)."""
     s = lat.stream
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(s)
-    lat.step(steps)
+    if stream_only:
+        lat.stream_only(steps)
+    else:
+        lat.step(steps)
     e1.record(s)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
@@ -106,6 +118,24 @@ def copy_ceiling(torch, gib=2.0, reps=20):
     del a, b
     torch.cuda.empty_cache()
     return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def pattern_ceilings(torch, n, reps=20):
+    """Bandwidth of the step's own memory streams without its stencil: the 19
+    planes of each z-slab copied, read and written in the step's layout and
+    launch shape (lbm_study_planes), all accesses aligned."""
+    from paper_1309_1983_amd import study
+    N = n ** 3
+    a = torch.rand(19 * N, device="cuda")
+    b = torch.empty_like(a)
+    sink = torch.zeros(4, device="cuda")
+    out = {}
+    for mode, nbytes in (("copy", 2 * 19 * N * 4), ("read", 19 * N * 4), ("write", 19 * N * 4)):
+        ms = _time_ms(torch, lambda: study.planes(mode, a, b, sink, n, n, n), reps)
+        out[f"planes19_{mode}_gbs"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def step_time_distribution(torch, n, steps, tau, lid):
@@ -319,6 +349,55 @@ def cpu_baseline(n, tau, lid, budget_s=12.0, single_budget_s=8.0):
                            "sample": f"{steps1} FP64 steps of the same cavity on 1 thread ({dt1:.1f} s)"}}
 
 
+def profile_workload(torch, what, steps):
+    """A few launches of one workload's kernels, for counter and trace runs
+    (rocprofv3 --pmc / --kernel-trace); prints only progress."""
+    import workloads as W
+    from paper_1309_1983_amd import Lattice, copy_f32, study
+    if what == "copy":
+        n = (2 << 30) // 4
+        a = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
+        b = torch.empty_like(a)
+        sink = torch.empty(4, device="cuda")
+        for _ in range(5):
+            copy_f32(a, b)                                     # non-temporal loads and stores
+        for _ in range(5):
+            study.stream("copy", a, b, sink, n, 1, 0, 0, 4)    # plain 16-byte loads and stores
+        torch.cuda.synchronize()
+        log("copy probes done: 2 GiB read and 2 GiB written per launch")
+    elif what == "cavity":
+        n = 256
+        for storage in ("f32", "f16", "bf16"):
+            lat = cavity_lattice(n, storage, "ab", 0.6, 0.1)
+            log(f"{storage}: {lat.step_kernel_name()}")
+            lat.step(steps)
+            if storage == "f32":
+                lat.stream_only(steps)
+            lat.sync()
+            lat.close()
+        log(f"cavity {n}^3: {steps} steps per storage, and {steps} FP32 stream-only steps")
+    elif what == "spheres":
+        flags = W.sphere_duct_flags(128, 128, 256, seed=20130909, solid_fraction=0.10)
+        for storage, pattern in (("f32", "ab"), ("f16", "ab"), ("bf16", "ab"), ("f32", "aa"), ("f16", "aa")):
+            lat = Lattice(128, 128, 256, 0.7, flags=flags, storage=storage, pattern=pattern)
+            lat.set_force((0.0, 0.0, 1e-6))
+            log(f"{storage} {pattern}: {lat.step_kernel_name()}")
+            lat.step(steps)
+            lat.sync()
+            lat.close()
+        log(f"sphere duct 128x128x256: {steps} steps per storage and pattern")
+    elif what == "adjoint":
+        n, T, K = 256, 8, 4
+        flags = W.duct_flags(n, n, n)
+        N = flags.size
+        lat = Lattice(n, n, n, 0.7, flags=flags)
+        lat.set_force(torch.from_numpy(W.random_force_field(N, 1, 1e-5).astype(np.float32)).cuda())
+        lat.forward_checkpointed(T, K)
+        lat.adjoint(torch.full((3, N), 1e-3, device="cuda"))
+        lat.close()
+        log(f"adjoint {n}^3 duct: T = {T}, K = {K}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,6 +414,11 @@ def main():
     ap.add_argument("--cavity", action="store_true",
                     help="run the cavity validation (Section 5: Re 100, 400, 1000 with on-site "
                          "walls, Eq. (8) scaling, doubled resolutions) instead")
+    ap.add_argument("--profile", choices=["cavity", "spheres", "adjoint", "copy"], default=None,
+                    help="run a few launches of one workload's kernels for rocprofv3 and exit: "
+                         "cavity (256^3 FP32/FP16/BF16 steps and the FP32 stream-only step), spheres "
+                         "(sphere duct, every storage, AB and AA), adjoint (256^3 reverse sweep, T=8, "
+                         "K=4), copy (the copy probe with and without load hints, 2 GiB)")
     ap.add_argument("--copy-only", action="store_true",
                     help="run only the copy probe (2 GiB float32, 20 launches): counter calibration")
     args = ap.parse_args()
@@ -369,6 +453,10 @@ def main():
         print(json.dumps({"cavity_validation": summary}), flush=True)
         return
 
+    if args.profile:
+        profile_workload(torch, args.profile, max(1, min(args.steps, 20)))
+        return
+
     if args.copy_only:
         cc = copy_ceiling(torch)
         print(json.dumps({"copy_gbs": round(cc, 1), "bytes_per_launch": 2 * (2 << 30)}), flush=True)
@@ -401,9 +489,10 @@ def main():
 
     # ---- headline: FP32 two-array step ----
     lat = cavity_lattice(n, "f32", "ab", tau, lid, block=args.block)
+    kernel_name = lat.step_kernel_name()     # the kernel the library's dispatch launches
     lat.step(args.warmup)
     torch.cuda.synchronize()
-    log(f"timing {args.steps} FP32 AB steps")
+    log(f"timing {args.steps} FP32 AB steps ({kernel_name})")
     ms = time_steps(lat, args.steps, torch)
     lat.check_finite()
     lat.close()
@@ -423,8 +512,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
                      "bytes_per_point": BYTES_PER_POINT["f32"],
-                     "kernel": ("k_step_abv<StF32, FORCE_NONE, COLLIDE, VW=4>" if n % 4 == 0
-                                else "k_step_ab<StF32, FORCE_NONE, COLLIDE>")},
+                     "kernel": kernel_name},
     }
     log(f"FP32 AB: {ms:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
@@ -437,6 +525,19 @@ def main():
         extra["copy_ceiling_gbs"] = round(cc, 1)
         line["roofline"]["frac_of_copy_ceiling"] = round(achieved / cc, 4)
         log(f"copy ceiling {cc:.0f} GB/s")
+        # the access pattern's own ceiling: the same gather and stores with no
+        # collision (lbm_debug_stream_only), and the 19 planes without shifts
+        lat = cavity_lattice(n, "f32", "ab", tau, lid, block=args.block)
+        lat.stream_only(args.warmup)
+        m = time_steps(lat, args.steps, torch, stream_only=True)
+        lat.close()
+        gbs = BYTES_PER_POINT["f32"] * N / (m * 1e-3) / 1e9
+        extra["stream_only_f32_ab"] = {"mlups": round(N / m / 1e3, 1), "ms_per_step": round(m, 5),
+                                       "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                       "step_time_over_stream_only": round(ms / m, 4)}
+        log(f"stream only (no collision): {m:.4f} ms/step, {gbs:.0f} GB/s; step/stream-only = {ms / m:.4f}")
+        extra["pattern_ceilings"] = pattern_ceilings(torch, n) if n % 4 == 0 else None
+        log(f"pattern ceilings: {extra['pattern_ceilings']}")
         for storage, pattern, cpl in (("f16", "ab", 0), ("bf16", "ab", 0), ("f16", "ab", 4),
                                       ("bf16", "ab", 4), ("f16", "aa", 0), ("bf16", "aa", 0),
                                       ("f32", "aa", 0)):
@@ -486,14 +587,19 @@ def main():
                                              "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                                              "bytes_per_point": bpp}
         log(f"f32_ab with rho,u every step: {m:.4f} ms/step, {N / m / 1e3:.0f} MLUPS, {gbs:.0f} GB/s")
-        try:
-            ar, gb = adjoint_rate(torch, n, T=200, K=50, tau=0.7)
-            extra["adjoint"] = {"mlups": round(ar, 1), "T": 200, "K": 50, "device_gb": round(gb, 1),
-                                "workload": f"duct {n}^3, per-point force, tau 0.7",
-                                "gbs_alg": round(ar * 1e6 * ADJOINT_BYTES_PER_POINT / 1e9, 1)}
-            log(f"adjoint: {ar:.0f} MLUPS (reverse sweep incl. recompute), {gb:.0f} GB on device")
-        except Exception as e:  # noqa: BLE001
-            extra["adjoint"] = {"error": str(e)}
+        for key, an, T, K in (("adjoint", n, 200, 50), ("adjoint64", 64, 200, 20)):
+            try:
+                ar, gb = adjoint_rate(torch, an, T=T, K=K, tau=0.7)
+                gbs = ar * 1e6 * ADJOINT_BYTES_PER_POINT / 1e9
+                extra[key] = {"mlups": round(ar, 1), "T": T, "K": K, "device_gb": round(gb, 2),
+                              "workload": f"duct {an}^3, per-point force, tau 0.7",
+                              "bytes_per_point": ADJOINT_BYTES_PER_POINT, "gbs_alg": round(gbs, 1),
+                              "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                if an <= 64:
+                    extra[key]["note"] = "20 MB states: largely cache-resident, no roofline claim"
+                log(f"{key}: {ar:.0f} MLUPS (reverse sweep incl. recompute), {gb:.1f} GB on device")
+            except Exception as e:  # noqa: BLE001
+                extra[key] = {"error": str(e)}
         log("other workload configurations")
         extra["configs"] = config_rates(torch, args.steps)
         for k, v in extra["configs"].items():

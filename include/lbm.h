@@ -109,6 +109,13 @@ typedef struct lbm_options {
                              solid neighbour), 1 = flags first, 2 = early
                              gather (the 19 loads are issued before the point
                              flags are examined). Results are identical. */
+    int groups_per_cu;    /* multi-point AB step: work-groups resident per
+                             compute unit. 0 = automatic (8 for FP32 storage
+                             with the default work-group shape when the flags
+                             come first, else as many as the registers allow),
+                             -1 = as many as the registers allow, 1..64 = that
+                             cap (LDS is reserved per work-group, never used).
+                             Results are identical. */
     void* population_dev[2]; /* optional caller-owned device buffers for the
                              population arrays: both NULL = the library
                              allocates them; otherwise the AB pattern needs
@@ -201,6 +208,14 @@ lbm_status lbm_get_info(const lbm_lattice* lat, int* nx, int* ny, int* nz, int* 
  * new one (an event recorded on the old stream is waited for on the new one;
  * the host does not block). */
 lbm_status lbm_set_stream(lbm_lattice* lat, void* hip_stream);
+
+/* Name of the device kernel the next lbm_step launches (the fused step of
+ * Algorithm 3 in the variant the lattice's storage, pattern, parity, force
+ * and geometry select), as the HIP runtime reports it, demangled; written to
+ * buf (NUL-terminated, truncated to cap bytes). For measurement tools that
+ * match it against profiler traces. Errors: LBM_ERR_INVALID for a NULL or
+ * empty buffer. */
+lbm_status lbm_step_kernel_name(lbm_lattice* lat, char* buf, size_t cap);
 
 /* Relaxation time (Eq. (2)); tau > 0.5. Invalidates a recorded trajectory. */
 lbm_status lbm_set_tau(lbm_lattice* lat, float tau);

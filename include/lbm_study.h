@@ -57,6 +57,21 @@ lbm_status lbm_study_shift(const float* src, float* dst, int nx, int nrows, int 
                            void* hip_stream);
 
 /*
+ * The memory streams of the step without its stencil (Section 4.1: 19 loads
+ * and 19 stores of 4 bytes per point): 19 planes per z-slab in the lattice
+ * kernels' layout, plane (z, i) at element (z*19 + i)*nx*ny, row y at y*nx
+ * within it. One row per wave, four points (16 bytes) per work-item, every
+ * access aligned, the FP32 step's cache hints.
+ *   mode 0 (copy):  dst = src     (19*N floats each)
+ *   mode 1 (read):  reads src; sink is written only for data that never
+ *                   occur (it may hold one float)
+ *   mode 2 (write): dst[(z*19 + i)*nx*ny + y*nx + x..x+3] = {i, y*nx + x, 0, 1}
+ * nx % 4 == 0, nx*ny*nz < 2^30, src and dst 16-byte aligned.
+ */
+lbm_status lbm_study_planes(int mode, const float* src, float* dst, float* sink, int nx, int ny,
+                            int nz, void* hip_stream);
+
+/*
  * One fused D3Q19 BGK iteration, FP32, one lattice point per work-item, on
  * plain [19][N] arrays `a` -> `b` (distinct), flags_dev [N] (0 fluid,
  * nonzero solid; walls are halfway bounce-back at rest; periodic box; no

@@ -18,14 +18,14 @@ PATTERN = {"ab": 0, "aa": 1}
 EXPORTS = [
     "lbm_options_default", "lbm_create", "lbm_create_ex", "lbm_destroy", "lbm_query_buffer_sizes",
     "lbm_trajectory_bytes", "lbm_set_trajectory_buffer", "lbm_set_adjoint_buffer", "lbm_get_info",
-    "lbm_set_stream", "lbm_set_tau", "lbm_set_wall_velocity", "lbm_set_force_uniform",
+    "lbm_set_stream", "lbm_step_kernel_name", "lbm_set_tau", "lbm_set_wall_velocity", "lbm_set_force_uniform",
     "lbm_set_force_field", "lbm_init_equilibrium", "lbm_step", "lbm_step_macros", "lbm_macros",
     "lbm_get_populations", "lbm_set_populations", "lbm_debug_stream_only",
     "lbm_forward_checkpointed", "lbm_adjoint", "lbm_adjoint_noalloc", "lbm_check_finite", "lbm_step_times", "lbm_sync",
     "lbm_device_bytes", "lbm_status_string", "lbm_last_error", "lbm_copy_f32",
 ]
 # include/lbm_study.h
-STUDY_EXPORTS = ["lbm_study_stream", "lbm_study_shift", "lbm_study_step"]
+STUDY_EXPORTS = ["lbm_study_stream", "lbm_study_shift", "lbm_study_planes", "lbm_study_step"]
 
 
 class LBMError(RuntimeError):
@@ -46,6 +46,7 @@ class lbm_options(ctypes.Structure):
         ("device", ctypes.c_int),
         ("cells_per_lane", ctypes.c_int),
         ("gather_mode", ctypes.c_int),
+        ("groups_per_cu", ctypes.c_int),
         ("population_dev", ctypes.c_void_p * 2),
     ]
 
@@ -91,6 +92,7 @@ def lib():
         "lbm_set_adjoint_buffer": (c_int, [vp, vp, c_size]),
         "lbm_get_info": (c_int, [vp, ip, ip, ip, ip, ip]),
         "lbm_set_stream": (c_int, [vp, vp]),
+        "lbm_step_kernel_name": (c_int, [vp, ctypes.c_char_p, c_size]),
         "lbm_set_tau": (c_int, [vp, c_float]),
         "lbm_set_wall_velocity": (c_int, [vp, c_float, c_float, c_float]),
         "lbm_set_force_uniform": (c_int, [vp, c_float, c_float, c_float]),
@@ -114,6 +116,7 @@ def lib():
         "lbm_copy_f32": (c_int, [fp, fp, c_size, vp]),
         "lbm_study_stream": (c_int, [c_int, fp, fp, fp, c_size, c_int, c_int, c_int, c_int, vp]),
         "lbm_study_shift": (c_int, [fp, fp, c_int, c_int, c_int, vp]),
+        "lbm_study_planes": (c_int, [c_int, fp, fp, fp, c_int, c_int, c_int, vp]),
         "lbm_study_step": (c_int, [fp, fp, vp, c_int, c_int, c_int, c_float, c_int, c_int, vp]),
     }
     for name, (res, args) in sig.items():

@@ -27,6 +27,9 @@ struct StepArgs {
 struct Launch {
     dim3 grid, block;
     hipStream_t stream;
+    // Dynamic LDS reserved per work-group and never touched by the kernel:
+    // caps the work-groups resident on a compute unit (its LDS / shmem).
+    unsigned shmem = 0;
 };
 
 Launch make_launch(const d3q19::Dims& d, int bx, int by, hipStream_t s);
@@ -49,6 +52,13 @@ hipError_t launch_step_abv(int storage, int vw, bool collide, int force_mode, vo
                            const uint8_t* flags, const uint32_t* smask, const uint32_t* mmask,
                            const float* ffield, const StepArgs& args, const Launch& L,
                            float* rho = nullptr, float* u = nullptr, bool onsite = false);
+
+// The kernel (host-side function pointer) that launch_step_abv (vector) or
+// launch_step would launch with these arguments, without launching it.
+hipError_t resolve_step_kernel(bool vector, int storage, int pattern, int parity, int vw, bool collide,
+                               int force_mode, void* a, void* b, const uint8_t* flags, const uint32_t* smask,
+                               const uint32_t* mmask, const float* ffield, const StepArgs& args, const Launch& L,
+                               bool onsite, const void** kernel);
 
 // flags_in holds the caller's values 0..4 (fluid, wall, moving wall, on-site
 // node at rest, on-site node moving with u_w). flags_out = type bits (on-site

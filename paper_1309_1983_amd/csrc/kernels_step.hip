@@ -640,6 +640,15 @@ __global__ __launch_bounds__(256) void k_copy(const float* __restrict__ src, flo
 
 // ------------------------------- dispatch ----------------------------------
 
+// While t_resolve is set (resolve_step_kernel), the step dispatch records the
+// kernel it would launch instead of launching it.
+static thread_local const void** t_resolve = nullptr;
+#define STEP_LAUNCH(K, GRID, BLOCK, SHMEM, STREAM, ...)                         \
+    do {                                                                      \
+        if (t_resolve) *t_resolve = reinterpret_cast<const void*>(&K);        \
+        else hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);  \
+    } while (0)
+
 template <class St, int FM, bool ONSITE>
 static hipError_t step_fm(int pattern, int parity, bool collide, void* a, void* b,
                           const uint8_t* flags, const uint32_t* sm, const uint32_t* mm, const float* ff,
@@ -650,21 +659,21 @@ static hipError_t step_fm(int pattern, int parity, bool collide, void* a, void* 
     T* B = static_cast<T*>(b);
     if (pattern == 0) {
         if (collide && rho)
-            hipLaunchKernelGGL((k_step_ab<St, FM, true, true, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
+            STEP_LAUNCH((k_step_ab<St, FM, true, true, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
         else if (collide)
-            hipLaunchKernelGGL((k_step_ab<St, FM, true, false, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
+            STEP_LAUNCH((k_step_ab<St, FM, true, false, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
         else
-            hipLaunchKernelGGL((k_step_ab<St, FORCE_NONE, false, false, false>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
+            STEP_LAUNCH((k_step_ab<St, FORCE_NONE, false, false, false>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
     } else if (parity == 0) {
         if (collide)
-            hipLaunchKernelGGL((k_step_aa0<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
+            STEP_LAUNCH((k_step_aa0<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
         else
-            hipLaunchKernelGGL((k_step_aa0<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
+            STEP_LAUNCH((k_step_aa0<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
     } else {
         if (collide)
-            hipLaunchKernelGGL((k_step_aa1<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
+            STEP_LAUNCH((k_step_aa1<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
         else
-            hipLaunchKernelGGL((k_step_aa1<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
+            STEP_LAUNCH((k_step_aa1<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
     }
     return hipGetLastError();
 }
@@ -713,13 +722,13 @@ static hipError_t stepv_grid(bool collide, void* a, void* b, const uint8_t* flag
     B* Bp = static_cast<B*>(b);
     constexpr bool CAN_EARLY = sizeof(B) == 4 && !ONSITE;
     if (collide && rho)
-        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, true, ONSITE, FLAT, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        STEP_LAUNCH((k_step_abv<St, FM, true, VW, true, ONSITE, FLAT, false>), L.grid, L.block, L.shmem, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     else if (collide && CAN_EARLY && args.early)
-        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, false, ONSITE, FLAT, CAN_EARLY>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        STEP_LAUNCH((k_step_abv<St, FM, true, VW, false, ONSITE, FLAT, CAN_EARLY>), L.grid, L.block, L.shmem, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     else if (collide)
-        hipLaunchKernelGGL((k_step_abv<St, FM, true, VW, false, ONSITE, FLAT, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        STEP_LAUNCH((k_step_abv<St, FM, true, VW, false, ONSITE, FLAT, false>), L.grid, L.block, L.shmem, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     else
-        hipLaunchKernelGGL((k_step_abv<St, FORCE_NONE, false, VW, false, false, FLAT, false>), L.grid, L.block, 0, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
+        STEP_LAUNCH((k_step_abv<St, FORCE_NONE, false, VW, false, false, FLAT, false>), L.grid, L.block, L.shmem, L.stream, A, Bp, flags, sm, mm, ff, args, rho, u);
     return hipGetLastError();
 }
 
@@ -891,6 +900,21 @@ hipError_t launch_check_finite(int storage, int layout, const void* f, const uin
     case 2: return finite_st<StBF16>(layout, f, flags, flag, d, L);
     default: return finite_st<StF32>(layout, f, flags, flag, d, L);
     }
+}
+
+hipError_t resolve_step_kernel(bool vector, int storage, int pattern, int parity, int vw, bool collide,
+                               int force_mode, void* a, void* b, const uint8_t* flags, const uint32_t* smask,
+                               const uint32_t* mmask, const float* ffield, const StepArgs& args, const Launch& L,
+                               bool onsite, const void** kernel)
+{
+    *kernel = nullptr;
+    t_resolve = kernel;
+    const hipError_t e = vector ? launch_step_abv(storage, vw, collide, force_mode, a, b, flags, smask, mmask,
+                                                  ffield, args, L, nullptr, nullptr, onsite)
+                                : launch_step(storage, pattern, parity, collide, force_mode, a, b, flags, smask,
+                                              mmask, ffield, args, L, nullptr, nullptr, onsite);
+    t_resolve = nullptr;
+    return *kernel ? hipSuccess : (e != hipSuccess ? e : hipErrorInvalidValue);
 }
 
 hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s)

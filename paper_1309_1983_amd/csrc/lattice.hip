@@ -9,8 +9,11 @@
 // its reverse sweep.
 #include <hip/hip_runtime.h>
 
+#include <cxxabi.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -74,6 +77,7 @@ struct lbm_lattice {
     bool flat = false;             // vector AB step on a one-dimensional grid per plane
     bool onsite = false;           // has on-site velocity nodes (flags 3, 4)
     bool early = false;            // FP32 vector AB step gathers before the flag branches
+    unsigned shmem4 = 0;           // LDS reserved per vector-step work-group (residency cap)
     hipEvent_t order_ev = nullptr; // orders work across lbm_set_stream
 
     bool sticky = false;
@@ -180,11 +184,14 @@ lbmk::Launch launch4_of(const lbm_lattice* L)
         la.block = dim3(64, 1, 1);
         la.grid = dim3((unsigned)((groups + 63) / 64), 1, (unsigned)L->nz);
         la.stream = L->stream;
+        la.shmem = L->shmem4;
         return la;
     }
     d3q19::Dims q = L->dims;
     q.nx = L->nx / L->cpl;   // the grid counts groups of cpl points along x
-    return lbmk::make_launch(q, L->bx4, L->by4, L->stream);
+    lbmk::Launch la = lbmk::make_launch(q, L->bx4, L->by4, L->stream);
+    la.shmem = L->shmem4;
+    return la;
 }
 
 void default_block(int nx, int& bx, int& by)
@@ -356,6 +363,8 @@ lbm_status resolve_layout(int nx, int ny, int nz, const lbm_options& opt, Layout
     if (opt.storage < 0 || opt.storage > 2) return fail(LBM_ERR_INVALID, "unknown storage %d", opt.storage);
     if (opt.pattern < 0 || opt.pattern > 1) return fail(LBM_ERR_INVALID, "unknown pattern %d", opt.pattern);
     if (opt.gather_mode < 0 || opt.gather_mode > 2) return fail(LBM_ERR_INVALID, "unknown gather_mode %d", opt.gather_mode);
+    if (opt.groups_per_cu < -1 || opt.groups_per_cu > 64)
+        return fail(LBM_ERR_INVALID, "groups_per_cu must be -1, 0 or 1..64 (got %d)", opt.groups_per_cu);
     int bx = opt.block_x, by = opt.block_y;
     if (bx == 0 && by == 0) default_block(nx, bx, by);
     if (bx <= 0 || by <= 0 || bx * by > 1024) return fail(LBM_ERR_INVALID, "bad block shape %dx%d", bx, by);
@@ -408,6 +417,10 @@ d3q19::Dims dims_of(int nx, int ny, int nz)
 // Early gather from this fraction of fluid points next to a solid on (FP32
 // sphere duct, 10%: 126.7 -> 114.1 us per step; 256^3 cavity, 2%: 3% slower).
 constexpr double EARLY_GATHER_MIN_NEAR_FRACTION = 0.08;
+// Resident work-groups per compute unit of the FP32 multi-point AB step (one
+// wave each): 256^3 cavity on MI355X, 426 us per step at the 12 that the
+// kernel's registers allow, 412 us at 8, 415 us at 10, 438 us at 5.
+constexpr int AUTO_GROUPS_PER_CU_F32 = 8;
 
 }  // namespace
 
@@ -553,6 +566,28 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
     const bool early_ok = L->storage == LBM_STORAGE_F32 && L->pattern == LBM_PATTERN_AB && L->cpl > 1 && !L->onsite;
     L->early = early_ok && (opt.gather_mode == 2 ||
                             (opt.gather_mode == 0 && near_fraction >= EARLY_GATHER_MIN_NEAR_FRACTION));
+    // residency cap of the vector AB step
+    int cap = opt.groups_per_cu;
+    if (cap == 0)
+        cap = (L->cpl > 1 && L->storage == LBM_STORAGE_F32 && !L->early && opt.block_x == 0 && opt.block_y == 0)
+                  ? AUTO_GROUPS_PER_CU_F32 : -1;
+    if (cap > 0 && L->cpl > 1) {
+        int lds_cu = 0, lds_block = 0;
+        hipError_t e = hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) {
+            lbm_destroy(L);
+            return fail(LBM_ERR_DEVICE, "LDS size query: %s", hipGetErrorString(e));
+        }
+        // the largest multiple of 512 bytes that still fits `cap` groups
+        const unsigned sh = (unsigned)(lds_cu / cap) & ~511u;
+        if (sh == 0 || (int)sh > lds_block || lds_cu / (int)sh != cap) {
+            lbm_destroy(L);
+            return fail(LBM_ERR_INVALID, "groups_per_cu = %d cannot be set with %d bytes of LDS per compute unit", cap,
+                        lds_cu);
+        }
+        L->shmem4 = sh;
+    }
     *out = L;
     return LBM_OK;
 }
@@ -644,6 +679,28 @@ lbm_status lbm_set_adjoint_buffer(lbm_lattice* L, void* dev, size_t bytes)
         L->d_taupart = reinterpret_cast<double*>(base + 2 * sbr);
         L->taupart_n = nblk;
     }
+    return LBM_OK;
+}
+
+lbm_status lbm_step_kernel_name(lbm_lattice* L, char* buf, size_t cap)
+{
+    lbm_status st = usable(L);
+    if (st != LBM_OK) return st;
+    if (!buf || cap == 0) return fail(LBM_ERR_INVALID, "buffer is NULL or empty");
+    DeviceGuard guard(L->device);
+    const bool vector = L->pattern == LBM_PATTERN_AB && L->cpl > 1;
+    const void* fn = nullptr;
+    HIPCHK(L, lbmk::resolve_step_kernel(vector, L->storage, L->pattern, L->parity, L->cpl, true, force_mode(L),
+                                        L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags, L->d_smask, L->d_mmask,
+                                        L->d_force, step_args(L), vector ? launch4_of(L) : launch_of(L), L->onsite,
+                                        &fn));
+    const char* mangled = hipKernelNameRefByPtr(fn, L->stream);
+    if (!mangled) return fail(LBM_ERR_DEVICE, "the runtime does not name the step kernel");
+    int dst = -1;
+    char* dem = abi::__cxa_demangle(mangled, nullptr, nullptr, &dst);
+    const char* name = (dst == 0 && dem) ? dem : mangled;
+    std::snprintf(buf, cap, "%s", name);
+    std::free(dem);
     return LBM_OK;
 }
 

@@ -177,6 +177,45 @@ __global__ __launch_bounds__(1024) void k_push(const float* __restrict__ a, floa
     }
 }
 
+// --------------------------- 19-plane streams ------------------------------
+// The step's memory streams without the step: the 19 planes of a z-slab in
+// the lattice kernels' layout (plane (z, i) at (z*19 + i)*nx*ny, x fastest),
+// one row per wave, four x-points (16 bytes) per work-item, every access
+// aligned, with the FP32 step's cache hints (non-temporal loads, buffer
+// stores with the non-temporal bit). MODE 0 copies src to dst, 1 reads src
+// (a never-taken store keeps the loads), 2 writes dst. The plane layout and
+// launch shape are the step's, the neighbour shifts and the collision are
+// left out: this is the pattern's own bandwidth ceiling.
+template <int MODE>
+__global__ __launch_bounds__(64) void k_planes(const float* __restrict__ src, float* __restrict__ dst,
+                                               float* __restrict__ sink, Dims d)
+{
+    using V = typename Vec<float, 4>::t;
+    const uint32_t x0 = 4 * (blockIdx.x * blockDim.x + threadIdx.x);
+    const uint32_t y = blockIdx.y, z = blockIdx.z;
+    if (x0 >= (uint32_t)d.nx) return;
+    const uint32_t o = y * (uint32_t)d.nx + x0;
+    V q[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (MODE == 2) {
+            q[i] = V{(float)i, (float)o, 0.0f, 1.0f};
+        } else {
+            const float* P = plane(src, d, i, z);
+            q[i] = __builtin_nontemporal_load(reinterpret_cast<const V*>(P + o));
+        }
+    }
+    if (MODE == 1) {
+        V a = q[0];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) a += q[i];
+        if (a.x == -1234.5f && a.y == 4321.5f) sink[0] = a.z;   // data are never these values
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) stv_nt<4>(plane(dst, d, i, z), o, q[i]);
+}
+
 lbm_status launch_status(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_ERR_DEVICE; }
 
 }  // namespace
@@ -234,6 +273,30 @@ lbm_status lbm_study_shift(const float* src, float* dst, int nx, int nrows, int 
         break;
     }
     default: return LBM_ERR_INVALID;
+    }
+    return launch_status(hipGetLastError());
+}
+
+lbm_status lbm_study_planes(int mode, const float* src, float* dst, float* sink, int nx, int ny, int nz,
+                            void* hip_stream)
+{
+    if (mode < 0 || mode > 2 || nx < 4 || nx % 4 || ny < 1 || nz < 1 || ny > 65535 || nz > 65535)
+        return LBM_ERR_INVALID;
+    if ((unsigned long long)nx * ny * nz >= (1ull << 30)) return LBM_ERR_INVALID;
+    if ((mode != 2 && !src) || (mode != 1 && !dst) || (mode == 1 && !sink)) return LBM_ERR_INVALID;
+    if ((((uintptr_t)src) | ((uintptr_t)dst)) & 15u) return LBM_ERR_INVALID;
+    Dims d{};
+    d.nx = nx; d.ny = ny; d.nz = nz;
+    d.nxy = (uint32_t)nx * (uint32_t)ny;
+    d.N = (uint32_t)((size_t)nx * ny * nz);
+    const unsigned groups = (unsigned)(nx / 4);
+    const unsigned bx = groups < 64 ? groups : 64;
+    const dim3 grid((groups + bx - 1) / bx, (unsigned)ny, (unsigned)nz), block(bx);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    switch (mode) {
+    case 0: hipLaunchKernelGGL(k_planes<0>, grid, block, 0, s, src, dst, sink, d); break;
+    case 1: hipLaunchKernelGGL(k_planes<1>, grid, block, 0, s, src, dst, sink, d); break;
+    default: hipLaunchKernelGGL(k_planes<2>, grid, block, 0, s, src, dst, sink, d); break;
     }
     return launch_status(hipGetLastError());
 }

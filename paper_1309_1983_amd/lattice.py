@@ -35,7 +35,7 @@ class Lattice:
 
     def __init__(self, nx, ny, nz, tau, flags=None, storage="f32", pattern="ab", block=None,
                  timing=0, check_interval=0, device=None, stream=None, cells_per_lane=0,
-                 gather_mode="auto", torch_buffers=False):
+                 gather_mode="auto", groups_per_cu=0, torch_buffers=False):
         if not torch.cuda.is_available():
             raise RuntimeError("Lattice needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
@@ -57,6 +57,7 @@ class Lattice:
         opt.device = self.device.index
         opt.cells_per_lane = int(cells_per_lane)
         opt.gather_mode = self.GATHER_MODES[gather_mode]
+        opt.groups_per_cu = int(groups_per_cu)
         # torch_buffers: the population arrays, the adjoint workspace and the
         # checkpoint store are torch allocations handed to the library
         self.torch_buffers = bool(torch_buffers)
@@ -192,6 +193,12 @@ class Lattice:
         n = ctypes.c_int(0)
         _abi.call("lbm_step_times", self._h, buf, cap, ctypes.byref(n))
         return np.frombuffer(buf, dtype=np.float32, count=n.value).copy()
+
+    def step_kernel_name(self):
+        """Demangled name of the kernel the next step() launches."""
+        buf = ctypes.create_string_buffer(512)
+        _abi.call("lbm_step_kernel_name", self._h, buf, ctypes.c_size_t(len(buf)))
+        return buf.value.decode()
 
     def device_bytes(self):
         return int(_abi.lib().lbm_device_bytes(self._h))

@@ -37,6 +37,11 @@ def shift(src, dst, nx, nrows, method, stream=None):
                                           _s(stream)), "lbm_study_shift")
 
 
+def planes(mode, src, dst, sink, nx, ny, nz, stream=None):
+    _abi.check(_abi.lib().lbm_study_planes(STREAM_MODES[mode], _p(src), _p(dst), _p(sink), nx, ny, nz,
+                                           _s(stream)), "lbm_study_planes")
+
+
 def step(a, b, flags, nx, ny, nz, tau, scheme, block_x=256, stream=None):
     _abi.check(_abi.lib().lbm_study_step(_p(a), _p(b), _p(flags), nx, ny, nz, ctypes.c_float(tau),
                                          SCHEMES[scheme], block_x, _s(stream)), "lbm_study_step")

@@ -120,6 +120,8 @@ def test_create_rejects_bad_modes_and_caller_buffers(abi):
         return opt
     cases = [
         (dict(gather_mode=-1), "gather_mode"),
+        (dict(groups_per_cu=-2), "groups_per_cu"),
+        (dict(groups_per_cu=65), "groups_per_cu"),
         (dict(population_dev=(4096, None)), "population_dev[1] is NULL"),
         (dict(population_dev=(4096 + 64, 8192)), "256-byte aligned"),
         (dict(population_dev=(4096, 4096)), "different"),
@@ -191,6 +193,10 @@ def test_study_calls_reject_bad_arguments(abi):
     assert L.lbm_study_stream(3, None, None, None, 1024, 19, 0, 0, 4, None) == abi.LBM_ERR_INVALID
     assert L.lbm_study_shift(None, None, 256, 4, 0, None) == abi.LBM_ERR_INVALID
     assert L.lbm_study_step(None, None, None, 8, 8, 8, ctypes.c_float(0.8), 0, 64, None) == abi.LBM_ERR_INVALID
+    assert L.lbm_study_planes(0, None, None, None, 256, 4, 4, None) == abi.LBM_ERR_INVALID
+    assert L.lbm_study_planes(3, ctypes.c_void_p(4096), ctypes.c_void_p(8192), None, 256, 4, 4, None) == abi.LBM_ERR_INVALID
+    assert L.lbm_study_planes(0, ctypes.c_void_p(4096), ctypes.c_void_p(8192), None, 254, 4, 4, None) == abi.LBM_ERR_INVALID
+    assert L.lbm_study_planes(0, ctypes.c_void_p(4100), ctypes.c_void_p(8192), None, 256, 4, 4, None) == abi.LBM_ERR_INVALID
 
 
 def test_status_strings(abi):

@@ -1,7 +1,7 @@
 """Launch modes and caller-owned memory change nothing in the results.
 
-- the gather modes (flags first / early gather) of the multi-point AB step
-  give bit-identical states;
+- the gather modes (flags first / early gather) and residency caps of the
+  multi-point AB step give bit-identical states;
 - populations, the checkpoint store and the adjoint workspace may be
   torch allocations handed to the library: states, macroscopic fields and
   adjoint gradients are bit-identical to library-allocated runs, and
@@ -64,6 +64,21 @@ def test_gather_modes_are_bitwise_equal_f32(case):
         np.testing.assert_array_equal(got[0][:, fl], ref[0][:, fl], err_msg=gm)
         np.testing.assert_array_equal(got[1], ref[1])
         np.testing.assert_array_equal(got[2], ref[2])
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_residency_cap_does_not_change_results(storage):
+    """Capping the resident work-groups per compute unit (reserved LDS) only
+    changes the schedule: bitwise equal to the uncapped run."""
+    shape = (64, 33, 21)
+    N = int(np.prod(shape))
+    flags = W.random_flags(N, seed=66, solid_fraction=0.1, moving_fraction=0.05)
+    s0 = near_rest_state(N, 67)
+    ref = _run(shape, 0.7, flags, s0, 6, force=(1e-5, 2e-5, 0), storage=storage, groups_per_cu=-1)
+    for gpc in (0, 3, 8):
+        got = _run(shape, 0.7, flags, s0, 6, force=(1e-5, 2e-5, 0), storage=storage, groups_per_cu=gpc)
+        for a, b in zip(got, ref):
+            np.testing.assert_array_equal(a, b)
 
 
 def test_porous_geometry_takes_early_gather_and_matches_one_point_kernel():

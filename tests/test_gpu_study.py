@@ -46,6 +46,31 @@ def test_stream_modes_move_the_right_elements(width, nvec, roff, woff):
     assert torch.equal(dst[:, woff:woff + n - 1], k[None, :] + v)
 
 
+@pytest.mark.parametrize("shape", [(256, 6, 5), (36, 7, 3), (1028, 2, 2)])
+def test_plane_streams_move_the_right_elements(shape):
+    """The 19-plane stream kernel: copy is exact, write stores the stated
+    pattern, read leaves the sink alone (its guard never fires)."""
+    from paper_1309_1983_amd import study
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    g = torch.Generator(device="cuda").manual_seed(nx)
+    src = torch.rand(19 * N, device="cuda", generator=g)
+    dst = torch.zeros(19 * N, device="cuda")
+    study.planes("copy", src, dst, None, nx, ny, nz)
+    assert torch.equal(dst, src)
+    sink = torch.full((4,), 7.0, device="cuda")
+    study.planes("read", src, None, sink, nx, ny, nz)
+    assert torch.equal(sink, torch.full((4,), 7.0, device="cuda"))
+    dst.zero_()
+    study.planes("write", None, dst, None, nx, ny, nz)
+    v = dst.view(nz, 19, ny * nx // 4, 4)
+    i = torch.arange(19, device="cuda", dtype=torch.float32).view(1, 19, 1)
+    o = (4 * torch.arange(ny * nx // 4, device="cuda", dtype=torch.float32)).view(1, 1, -1)
+    assert torch.equal(v[..., 0], i.expand(nz, 19, ny * nx // 4))
+    assert torch.equal(v[..., 1], o.expand(nz, 19, ny * nx // 4))
+    assert torch.all(v[..., 2] == 0) and torch.all(v[..., 3] == 1)
+
+
 @pytest.mark.parametrize("method", ["direct", "lds", "dpp", "direct4"])
 @pytest.mark.parametrize("nx", [64, 256, 1024])
 def test_shift_methods_are_a_periodic_roll(method, nx):
