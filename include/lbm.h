@@ -97,8 +97,10 @@ typedef struct lbm_options {
                              this many steps (synchronises the stream) */
     int device;           /* HIP device ordinal; -1 = the current device */
     int cells_per_lane;   /* AB step: points per work-item. 0 = automatic (8
-                             for 16-bit storage when nx % 8 == 0 and
-                             nx >= 256, else 4 when nx % 4 == 0, else 1);
+                             for 16-bit storage when nx % 8 == 0 and either
+                             nx >= 256 or at least 8% of the fluid points have
+                             a solid neighbour, else 4 when nx % 4 == 0,
+                             else 1);
                              1; 4; or 8 (16-bit storage only: 16-byte
                              accesses). 4 and 8 need
                              nx to be a multiple of them and

@@ -381,13 +381,13 @@ hipError_t launch_adjoint_seed(int fm, const float* f, const uint8_t* flags, con
 {
     switch (fm) {
     case FORCE_UNIFORM:
-        hipLaunchKernelGGL((k_adj_seed<FORCE_UNIFORM>), L.grid, L.block, 0, L.stream, f, flags, ff, g, aout, gF, args);
+        hipLaunchKernelGGL((k_adj_seed<FORCE_UNIFORM>), L.grid, L.block, L.shmem, L.stream, f, flags, ff, g, aout, gF, args);
         break;
     case FORCE_FIELD:
-        hipLaunchKernelGGL((k_adj_seed<FORCE_FIELD>), L.grid, L.block, 0, L.stream, f, flags, ff, g, aout, gF, args);
+        hipLaunchKernelGGL((k_adj_seed<FORCE_FIELD>), L.grid, L.block, L.shmem, L.stream, f, flags, ff, g, aout, gF, args);
         break;
     default:
-        hipLaunchKernelGGL((k_adj_seed<FORCE_NONE>), L.grid, L.block, 0, L.stream, f, flags, ff, g, aout, gF, args);
+        hipLaunchKernelGGL((k_adj_seed<FORCE_NONE>), L.grid, L.block, L.shmem, L.stream, f, flags, ff, g, aout, gF, args);
     }
     return hipGetLastError();
 }
@@ -398,9 +398,9 @@ static hipError_t adj_fm(bool direct, const float* s, const float* bin, float* b
                          float it2, const Launch& L)
 {
     if (direct)
-        hipLaunchKernelGGL((k_adj_step<FM, true>), L.grid, L.block, 0, L.stream, s, bin, bout, gF, tp, flags, ff, a, it2);
+        hipLaunchKernelGGL((k_adj_step<FM, true>), L.grid, L.block, L.shmem, L.stream, s, bin, bout, gF, tp, flags, ff, a, it2);
     else
-        hipLaunchKernelGGL((k_adj_step<FM, false>), L.grid, L.block, 0, L.stream, s, bin, bout, gF, tp, flags, ff, a, it2);
+        hipLaunchKernelGGL((k_adj_step<FM, false>), L.grid, L.block, L.shmem, L.stream, s, bin, bout, gF, tp, flags, ff, a, it2);
     return hipGetLastError();
 }
 
@@ -410,9 +410,9 @@ static hipError_t adjv_fm(bool direct, const float* s, const float* bin, float* 
                           const float* ff, const StepArgs& a, float it2, const Launch& L)
 {
     if (direct)
-        hipLaunchKernelGGL((k_adj_stepv<FM, true, VW>), L.grid, L.block, 0, L.stream, s, bin, bout, gF, tp, flags, sm, mm, ff, a, it2);
+        hipLaunchKernelGGL((k_adj_stepv<FM, true, VW>), L.grid, L.block, L.shmem, L.stream, s, bin, bout, gF, tp, flags, sm, mm, ff, a, it2);
     else
-        hipLaunchKernelGGL((k_adj_stepv<FM, false, VW>), L.grid, L.block, 0, L.stream, s, bin, bout, gF, tp, flags, sm, mm, ff, a, it2);
+        hipLaunchKernelGGL((k_adj_stepv<FM, false, VW>), L.grid, L.block, L.shmem, L.stream, s, bin, bout, gF, tp, flags, sm, mm, ff, a, it2);
     return hipGetLastError();
 }
 

@@ -8,6 +8,8 @@
 // d3q19.hpp): the structure-of-arrays coalescing of Section 4.1, with the 19
 // planes of a slab next to each other so that the concurrently running
 // work-groups stream through a compact address window.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 using namespace d3q19;
@@ -181,17 +183,20 @@ struct FlagWord<8> {
 // work-item; fully solid groups then run the whole path and store the rest
 // state like solid points in mixed groups, and waves with no fluid point
 // store nothing.
-template <class St, int VW, bool ONSITE>
+template <class St, int FM, int VW, bool MACROS, bool ONSITE>
 struct Occupancy {
     // Waves per SIMD the register budget must allow: the 16-bit eight-point
     // step sits at the 168-VGPR edge of three waves per SIMD, and losing the
-    // third wave cost 11% at 256^3 on MI355X; the on-site variants need more
-    // registers than three waves allow and keep two.
-    static constexpr int waves = (VW == 8 && !ONSITE) ? 3 : 1;
+    // third wave cost 11% at 256^3 on MI355X. Variants that need more (the
+    // macroscopic output, on-site nodes, bfloat16 with a body force) would
+    // spill under that bound and keep two waves.
+    static constexpr bool tight = VW == 8 && !ONSITE && !MACROS &&
+                                  (sizeof(typename St::raw_t) == 2 && (!std::is_same_v<St, StBF16> || FM == FORCE_NONE));
+    static constexpr int waves = tight ? 3 : 1;
 };
 
 template <class St, int FM, bool COLLIDE, int VW, bool MACROS, bool ONSITE, bool FLAT, bool EARLY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<St, VW, ONSITE>::waves)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Occupancy<St, FM, VW, MACROS, ONSITE>::waves)))
 void k_step_abv(const typename St::bits_t* __restrict__ src,
                                                   typename St::bits_t* __restrict__ dst,
                                                   const uint8_t* __restrict__ flags,
@@ -659,21 +664,21 @@ static hipError_t step_fm(int pattern, int parity, bool collide, void* a, void* 
     T* B = static_cast<T*>(b);
     if (pattern == 0) {
         if (collide && rho)
-            STEP_LAUNCH((k_step_ab<St, FM, true, true, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
+            STEP_LAUNCH((k_step_ab<St, FM, true, true, ONSITE>), L.grid, L.block, L.shmem, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
         else if (collide)
-            STEP_LAUNCH((k_step_ab<St, FM, true, false, ONSITE>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
+            STEP_LAUNCH((k_step_ab<St, FM, true, false, ONSITE>), L.grid, L.block, L.shmem, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
         else
-            STEP_LAUNCH((k_step_ab<St, FORCE_NONE, false, false, false>), L.grid, L.block, 0, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
+            STEP_LAUNCH((k_step_ab<St, FORCE_NONE, false, false, false>), L.grid, L.block, L.shmem, L.stream, A, B, flags, sm, mm, ff, args, rho, u);
     } else if (parity == 0) {
         if (collide)
-            STEP_LAUNCH((k_step_aa0<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
+            STEP_LAUNCH((k_step_aa0<St, FM, true, ONSITE>), L.grid, L.block, L.shmem, L.stream, A, flags, sm, mm, ff, args);
         else
-            STEP_LAUNCH((k_step_aa0<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
+            STEP_LAUNCH((k_step_aa0<St, FORCE_NONE, false, false>), L.grid, L.block, L.shmem, L.stream, A, flags, sm, mm, ff, args);
     } else {
         if (collide)
-            STEP_LAUNCH((k_step_aa1<St, FM, true, ONSITE>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
+            STEP_LAUNCH((k_step_aa1<St, FM, true, ONSITE>), L.grid, L.block, L.shmem, L.stream, A, flags, sm, mm, ff, args);
         else
-            STEP_LAUNCH((k_step_aa1<St, FORCE_NONE, false, false>), L.grid, L.block, 0, L.stream, A, flags, sm, mm, ff, args);
+            STEP_LAUNCH((k_step_aa1<St, FORCE_NONE, false, false>), L.grid, L.block, L.shmem, L.stream, A, flags, sm, mm, ff, args);
     }
     return hipGetLastError();
 }
