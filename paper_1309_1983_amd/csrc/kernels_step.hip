@@ -74,24 +74,6 @@ __device__ __forceinline__ Macro decode_collide(const typename St::raw_t raw[Q],
     const uint32_t c = z * (d).nxy + o;                                                        \
     const uint32_t zm = wrap_m(z, (uint32_t)(d).nz), zp = wrap_p(z, (uint32_t)(d).nz);
 
-// Rest state (f_i = w_i: offset 0) of VW consecutive points at o0 of slab z.
-// The vector two-array step writes it for a fully solid group whose wave
-// also holds fluid points, although nothing reads it: leaving holes in a
-// wave's stores cost 17% of the step time on the 10%-solid sphere duct
-// (measured on MI355X). Waves with no fluid point skip their stores
-// entirely. The one-point kernels do not write solid points: there the
-// stores measured 6-8% slower.
-template <class St, int VW, class P>
-__device__ __forceinline__ void store_rest(P* fp, const Dims& d, uint32_t z, uint32_t o0)
-{
-    typename St::bits_t* f = reinterpret_cast<typename St::bits_t*>(fp);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const typename Vec<typename St::bits_t, VW>::t r = St::enc_b(0.0f, i);
-        stv_nt<VW>(plane(f, d, i, z), o0, r);
-    }
-}
-
 // ---------------------------------------------------------------------------
 // AB pull step, one point per work-item: gather from x - e_i in `src`,
 // bounce back at solid neighbours, collide, store into `dst`. Used when the
@@ -237,137 +219,148 @@ void k_step_abv(const typename St::bits_t* __restrict__ src,
         load_words<VW>(smask, c0, early_mask);
     } else {
         // wave-wide vote, taken by every work-item before the branch
-        const bool wave_fluid = __builtin_amdgcn_ballot_w64(solid != ONES) != 0ull;
-        if (solid == ONES) {
+        if (__builtin_amdgcn_ballot_w64(solid != ONES) == 0ull) {   // no fluid point in the wave
             if (MACROS) {
                 const typename Vec<float, VW>::t zero = 0.0f;
                 stv_nt<VW>(rho_out, c0, zero);
 #pragma unroll
                 for (int k = 0; k < 3; ++k) stv_nt<VW>(u_out + k * (size_t)d.N, c0, zero);
             }
-            if (wave_fluid) store_rest<St, VW>(dst, d, z, o0);
             return;
         }
     }
 
-    const uint32_t zm = wrap_m(z, (uint32_t)d.nz), zp = wrap_p(z, (uint32_t)d.nz);
-    const uint32_t oym = (y == 0) ? (uint32_t)(d.ny - 1) * nx : (uint32_t)0 - nx;
-    const uint32_t oyp = (y == d.ny - 1) ? (uint32_t)(1 - d.ny) * nx : nx;
-
     Vt q[Q];
-    gather_vec<+1, VW, EARLY>(src, d, z, zm, zp, orow, oym, oyp, (uint32_t)x0, !(solid & 0x1u),
-                              !((solid >> (8 * (VW - 1))) & 0x1u), (flw & (ONES * NEAR_WALL)) != 0, smask, c0,
-                              q, early_mask);
+    typename Vec<float, VW>::t mr, mx, my, mz;
+    if (!EARLY && solid == ONES) {
+        // Fully solid group in a wave that holds fluid points: the rest
+        // state (offset 0), although nothing reads it. Leaving holes in a
+        // wave's stores cost 17% of the step time on the 10%-solid sphere
+        // duct, and storing it apart from the fluid work-items' stores wrote
+        // the shared cache lines back twice (write traffic 9-14% above the
+        // state size with 16-bit storage); the same store instructions
+        // write both. Waves with no fluid point store nothing.
+#pragma unroll
+        for (int i = 0; i < Q; ++i) q[i] = St::enc_b(0.0f, i);
+        mr = 0.0f; mx = 0.0f; my = 0.0f; mz = 0.0f;
+    } else {
+        const uint32_t zm = wrap_m(z, (uint32_t)d.nz), zp = wrap_p(z, (uint32_t)d.nz);
+        const uint32_t oym = (y == 0) ? (uint32_t)(d.ny - 1) * nx : (uint32_t)0 - nx;
+        const uint32_t oyp = (y == d.ny - 1) ? (uint32_t)(1 - d.ny) * nx : nx;
 
-    // moving-wall terms of the bounced populations
-    uint32_t mm[VW];
+        gather_vec<+1, VW, EARLY>(src, d, z, zm, zp, orow, oym, oyp, (uint32_t)x0, !(solid & 0x1u),
+                                  !((solid >> (8 * (VW - 1))) & 0x1u), (flw & (ONES * NEAR_WALL)) != 0, smask, c0,
+                                  q, early_mask);
+
+        // moving-wall terms of the bounced populations
+        uint32_t mm[VW];
 #pragma unroll
-    for (int j = 0; j < VW; ++j) mm[j] = 0u;
-    if (COLLIDE && (flw & (ONES * NEAR_MOVING))) {
+        for (int j = 0; j < VW; ++j) mm[j] = 0u;
+        if (COLLIDE && (flw & (ONES * NEAR_MOVING))) {
 #pragma unroll
-        for (int g = 0; g < VW / 4; ++g) {
-            const typename V4<uint32_t>::t m4 = ld4(mmask, c0 + 4 * g);
-            mm[4 * g] = m4.x; mm[4 * g + 1] = m4.y; mm[4 * g + 2] = m4.z; mm[4 * g + 3] = m4.w;
+            for (int g = 0; g < VW / 4; ++g) {
+                const typename V4<uint32_t>::t m4 = ld4(mmask, c0 + 4 * g);
+                mm[4 * g] = m4.x; mm[4 * g + 1] = m4.y; mm[4 * g + 2] = m4.z; mm[4 * g + 3] = m4.w;
+            }
         }
-    }
-    uint32_t os[VW];   // unknown-direction bits of on-site nodes, else 0
+        uint32_t os[VW];   // unknown-direction bits of on-site nodes, else 0
 #pragma unroll
-    for (int j = 0; j < VW; ++j) os[j] = 0u;
-    if (ONSITE && COLLIDE && (flw & (ONES * ONSITE_NODE))) {
-        load_words<VW>(smask, c0, os);
+        for (int j = 0; j < VW; ++j) os[j] = 0u;
+        if (ONSITE && COLLIDE && (flw & (ONES * ONSITE_NODE))) {
+            load_words<VW>(smask, c0, os);
 #pragma unroll
-        for (int j = 0; j < VW; ++j)
-            if (!((flw >> (8 * j)) & ONSITE_NODE)) os[j] = 0u;
-    }
+            for (int j = 0; j < VW; ++j)
+                if (!((flw >> (8 * j)) & ONSITE_NODE)) os[j] = 0u;
+        }
 
-    if (COLLIDE) {
-        float F[3][VW];
-        if (FM == FORCE_FIELD) {
+        if (COLLIDE) {
+            float F[3][VW];
+            if (FM == FORCE_FIELD) {
 #pragma unroll
-            for (int k = 0; k < 3; ++k)
+                for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int g = 0; g < VW / 4; ++g) {
-                    const typename V4<float>::t f = ld4(ff + k * (size_t)d.N, c0 + 4 * g);
-                    F[k][4 * g] = f.x; F[k][4 * g + 1] = f.y; F[k][4 * g + 2] = f.z; F[k][4 * g + 3] = f.w;
+                    for (int g = 0; g < VW / 4; ++g) {
+                        const typename V4<float>::t f = ld4(ff + k * (size_t)d.N, c0 + 4 * g);
+                        F[k][4 * g] = f.x; F[k][4 * g + 1] = f.y; F[k][4 * g + 2] = f.z; F[k][4 * g + 3] = f.w;
+                    }
+            } else {
+#pragma unroll
+                for (int j = 0; j < VW; ++j) {
+                    F[0][j] = FM == FORCE_UNIFORM ? a.Fx : 0.0f;
+                    F[1][j] = FM == FORCE_UNIFORM ? a.Fy : 0.0f;
+                    F[2][j] = FM == FORCE_UNIFORM ? a.Fz : 0.0f;
                 }
-        } else {
+            }
+            // On-site nodes: the first on-site point of each work-item is rebuilt
+            // before the loop, so a wave whose on-site points sit at different
+            // positions in different work-items (the two ends of a row) runs the
+            // rebuild once rather than once per position; further on-site points
+            // of a work-item (rows lying on a face of the box) are rebuilt in the
+            // loop. The moving-wall terms are skipped for that point: they only
+            // touch its unknown directions, which the rebuild overwrites.
+            int jr = VW;
+            float hr[ONSITE ? Q : 1];
+            if (ONSITE) {
+                uint32_t Ur = 0u;
+#pragma unroll
+                for (int j = VW - 1; j >= 0; --j)
+                    if (os[j]) { jr = j; Ur = os[j]; }
+                if (Ur) {
+                    float fr[3];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        fr[k] = F[k][0];
+#pragma unroll
+                        for (int j = 1; j < VW; ++j) fr[k] = jr == j ? F[k][j] : fr[k];
+                    }
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) {
+                        B b = q[i][0];
+#pragma unroll
+                        for (int j = 1; j < VW; ++j) b = jr == j ? q[i][j] : b;
+                        hr[i] = St::off_b(b, i);
+                    }
+                    const bool mv = (flw >> (8 * jr)) & ONSITE_MOVING;
+                    onsite_rebuild<FM != FORCE_NONE>(hr, Ur, mv ? a.uw[0] : 0.0f, mv ? a.uw[1] : 0.0f,
+                                                     mv ? a.uw[2] : 0.0f, fr[0], fr[1], fr[2]);
+                }
+            }
 #pragma unroll
             for (int j = 0; j < VW; ++j) {
-                F[0][j] = FM == FORCE_UNIFORM ? a.Fx : 0.0f;
-                F[1][j] = FM == FORCE_UNIFORM ? a.Fy : 0.0f;
-                F[2][j] = FM == FORCE_UNIFORM ? a.Fz : 0.0f;
-            }
-        }
-        // On-site nodes: the first on-site point of each work-item is rebuilt
-        // before the loop, so a wave whose on-site points sit at different
-        // positions in different work-items (the two ends of a row) runs the
-        // rebuild once rather than once per position; further on-site points
-        // of a work-item (rows lying on a face of the box) are rebuilt in the
-        // loop. The moving-wall terms are skipped for that point: they only
-        // touch its unknown directions, which the rebuild overwrites.
-        int jr = VW;
-        float hr[ONSITE ? Q : 1];
-        if (ONSITE) {
-            uint32_t Ur = 0u;
-#pragma unroll
-            for (int j = VW - 1; j >= 0; --j)
-                if (os[j]) { jr = j; Ur = os[j]; }
-            if (Ur) {
-                float fr[3];
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    fr[k] = F[k][0];
-#pragma unroll
-                    for (int j = 1; j < VW; ++j) fr[k] = jr == j ? F[k][j] : fr[k];
-                }
+                float h[Q];
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    B b = q[i][0];
-#pragma unroll
-                    for (int j = 1; j < VW; ++j) b = jr == j ? q[i][j] : b;
-                    hr[i] = St::off_b(b, i);
+                    h[i] = St::off_b(q[i][j], i);
+                    if (i > 0 && ((mm[j] >> i) & 1u)) h[i] = h[i] + a.mw[i];
                 }
-                const bool mv = (flw >> (8 * jr)) & ONSITE_MOVING;
-                onsite_rebuild<FM != FORCE_NONE>(hr, Ur, mv ? a.uw[0] : 0.0f, mv ? a.uw[1] : 0.0f,
-                                                 mv ? a.uw[2] : 0.0f, fr[0], fr[1], fr[2]);
-            }
-        }
-        typename Vec<float, VW>::t mr, mx, my, mz;
+                if (ONSITE) {
+                    if (jr == j) {
 #pragma unroll
-        for (int j = 0; j < VW; ++j) {
-            float h[Q];
+                        for (int i = 0; i < Q; ++i) h[i] = hr[i];
+                    } else if (os[j]) {
+                        const bool mv = (flw >> (8 * j)) & ONSITE_MOVING;
+                        onsite_rebuild<FM != FORCE_NONE>(h, os[j], mv ? a.uw[0] : 0.0f, mv ? a.uw[1] : 0.0f,
+                                                         mv ? a.uw[2] : 0.0f, F[0][j], F[1][j], F[2][j]);
+                    }
+                }
+                const Macro m = bgk_collide<FM != FORCE_NONE>(h, a.omega, a.cF, F[0][j], F[1][j], F[2][j]);
+                const bool sol = (solid >> (8 * j)) & 1u;
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                h[i] = St::off_b(q[i][j], i);
-                if (i > 0 && ((mm[j] >> i) & 1u)) h[i] = h[i] + a.mw[i];
-            }
-            if (ONSITE) {
-                if (jr == j) {
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) h[i] = hr[i];
-                } else if (os[j]) {
-                    const bool mv = (flw >> (8 * j)) & ONSITE_MOVING;
-                    onsite_rebuild<FM != FORCE_NONE>(h, os[j], mv ? a.uw[0] : 0.0f, mv ? a.uw[1] : 0.0f,
-                                                     mv ? a.uw[2] : 0.0f, F[0][j], F[1][j], F[2][j]);
+                for (int i = 0; i < Q; ++i) q[i][j] = St::enc_b(sol ? 0.0f : h[i], i);
+                if (MACROS) {
+                    mr[j] = sol ? 0.0f : m.rho;
+                    mx[j] = sol ? 0.0f : m.ux;
+                    my[j] = sol ? 0.0f : m.uy;
+                    mz[j] = sol ? 0.0f : m.uz;
                 }
             }
-            const Macro m = bgk_collide<FM != FORCE_NONE>(h, a.omega, a.cF, F[0][j], F[1][j], F[2][j]);
-            const bool sol = (solid >> (8 * j)) & 1u;
-#pragma unroll
-            for (int i = 0; i < Q; ++i) q[i][j] = St::enc_b(sol ? 0.0f : h[i], i);
-            if (MACROS) {
-                mr[j] = sol ? 0.0f : m.rho;
-                mx[j] = sol ? 0.0f : m.ux;
-                my[j] = sol ? 0.0f : m.uy;
-                mz[j] = sol ? 0.0f : m.uz;
-            }
         }
-        if (MACROS) {
-            stv_nt<VW>(rho_out, c0, mr);
-            stv_nt<VW>(u_out, c0, mx);
-            stv_nt<VW>(u_out + (size_t)d.N, c0, my);
-            stv_nt<VW>(u_out + 2 * (size_t)d.N, c0, mz);
-        }
+    }
+    if (MACROS) {
+        stv_nt<VW>(rho_out, c0, mr);
+        stv_nt<VW>(u_out, c0, mx);
+        stv_nt<VW>(u_out + (size_t)d.N, c0, my);
+        stv_nt<VW>(u_out + 2 * (size_t)d.N, c0, mz);
     }
     if constexpr (EARLY) {
         if (__builtin_amdgcn_ballot_w64(solid != ONES) == 0ull) return;   // no fluid point in the wave
