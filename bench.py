@@ -57,9 +57,28 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+def _kernel_key(name):
+    """Kernel name without its parameter list (the template arguments stay)."""
+    name = name.strip()
+    if name.startswith("void "):
+        name = name[5:]
+    if not name.endswith(")"):
+        return name
+    depth = 0
+    for k in range(len(name) - 1, -1, -1):   # the last parenthesised group
+        if name[k] == ")":
+            depth += 1
+        elif name[k] == "(":
+            depth -= 1
+            if depth == 0:
+                return name[:k]
+    return name
+
+
+def load_traffic(workload, kernel_name):
+    """HBM bytes per launch of `kernel_name` from the committed rocprofv3
+    counter summary of `workload`, if it was taken on the current kernel
+    source (else None)."""
     path = os.path.join(ROOT, "profiles", f"pmc_traffic_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -67,7 +86,118 @@ def load_traffic(workload):
         d = json.load(fh)
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    for k in d.get("kernels", []):
+        if k["kernel"] == _kernel_key(kernel_name):
+            return k["hbm_bytes_per_launch"]
+    return None
+
+
+# ---- rocprofv3 counter summaries (run on the host after the counter passes) ----
+# Every pass is `rocprofv3 --pmc <counters> --output-format csv -d <DIR>/<pass>_<what>
+# -o run -- python3 bench.py --profile <what> --steps 10`, one pass per counter set:
+PMC_PASSES = {
+    "fetch": ["FETCH_SIZE"],
+    "write": ["WRITE_SIZE"],
+    "rdreq": ["TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_sum"],
+    "wrreq": ["TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum"],
+    "hit": ["TCC_HIT_sum", "TCC_MISS_sum"],
+}
+PMC_WORKLOADS = {   # --profile workload -> (summary name, lattice points)
+    "cavity": ("cavity256", 256 ** 3),
+    "spheres": ("spheres128x128x256", 128 * 128 * 256),
+    "adjoint": ("adjoint256", 256 ** 3),
+}
+COPY_BYTES_EACH_WAY = 2 << 30   # the copy probes of --profile copy: 2 GiB read, 2 GiB written
+
+
+def _pmc_table(path):
+    """{kernel key: {counter: [per-dispatch values]}} from one pass's CSV."""
+    import csv
+    out = {}
+    with open(os.path.join(path, "run_counter_collection.csv")) as fh:
+        for r in csv.DictReader(fh):
+            k = _kernel_key(r["Kernel_Name"])
+            if k.startswith("at::") or "rocclr" in k or "__amd_" in k:
+                continue
+            out.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def _algorithmic_bytes_per_point(kernel):
+    """State bytes one launch must move per lattice point (Section 4.1): 19
+    loads and 19 stores of the storage width for a step, plus the force field
+    when the step reads one; 264 B for the reverse step; None otherwise."""
+    if kernel.startswith("lbmk::k_adj_stepv"):
+        return ADJOINT_REVERSE_BYTES
+    for pre in ("lbmk::k_step_abv<", "lbmk::k_step_aa0<", "lbmk::k_step_aa1<"):
+        if kernel.startswith(pre):
+            args = [a.strip() for a in kernel[len(pre):-1].split(",")]
+            width = 4 if args[0].endswith("StF32") else 2
+            field = args[1] == "2"
+            return 2 * 19 * width + (FORCE_FIELD_BYTES if field else 0)
+    return None
+
+
+def pmc_summary(root, out_dir):
+    """Write profiles/pmc_traffic_<workload>.json from the counter passes under
+    `root`: per kernel the FETCH_SIZE / WRITE_SIZE figures scaled by what the
+    same counters read for the copy probes of known size, the exact EA
+    request bytes (128/64/32-byte read requests, 64/32-byte write requests)
+    and the L2 hit rate, all per dispatch."""
+    def mean(v):
+        return sum(v) / len(v)
+
+    cal = {p: _pmc_table(os.path.join(root, f"{p}_copy")) for p in ("fetch", "write")}
+    copies = sorted(cal["fetch"])
+    fetch_kib = mean([mean(cal["fetch"][k]["FETCH_SIZE"]) for k in copies])
+    write_kib = mean([mean(cal["write"][k]["WRITE_SIZE"]) for k in copies])
+    f_fac = COPY_BYTES_EACH_WAY / (fetch_kib * 1024)
+    w_fac = COPY_BYTES_EACH_WAY / (write_kib * 1024)
+    calibration = {"copy_kernels": copies, "copy_bytes_each_way": COPY_BYTES_EACH_WAY,
+                   "copy_fetch_size_kib_per_dispatch": round(fetch_kib, 1),
+                   "copy_write_size_kib_per_dispatch": round(write_kib, 1),
+                   "fetch_factor": round(f_fac, 5), "write_factor": round(w_fac, 5)}
+    written = []
+    for what, (name, npts) in PMC_WORKLOADS.items():
+        t = {p: _pmc_table(os.path.join(root, f"{p}_{what}")) for p in PMC_PASSES}
+        kernels = []
+        for k in t["fetch"]:
+            c = {}
+            for p in PMC_PASSES:
+                for cn, v in t[p].get(k, {}).items():
+                    c[cn] = mean(v)
+            rd = f_fac * c["FETCH_SIZE"] * 1024
+            wr = w_fac * c.get("WRITE_SIZE", 0.0) * 1024
+            e = {"kernel": k, "dispatches": len(t["fetch"][k]["FETCH_SIZE"]),
+                 "fetch_size_kib": round(c["FETCH_SIZE"], 1), "write_size_kib": round(c.get("WRITE_SIZE", 0.0), 1),
+                 "hbm_read_bytes": round(rd), "hbm_write_bytes": round(wr), "hbm_bytes_per_launch": round(rd + wr)}
+            if "TCC_EA0_RDREQ_sum" in c:
+                e["ea_read_bytes_from_request_sizes"] = round(
+                    32 * c["TCC_EA0_RDREQ_32B_sum"] + 64 * c["TCC_EA0_RDREQ_64B_sum"]
+                    + 128 * c["TCC_EA0_RDREQ_128B_sum"])
+            if "TCC_EA0_WRREQ_sum" in c:
+                e["ea_write_bytes_from_request_sizes"] = round(
+                    64 * c["TCC_EA0_WRREQ_64B_sum"] + 32 * (c["TCC_EA0_WRREQ_sum"] - c["TCC_EA0_WRREQ_64B_sum"]))
+            if "TCC_HIT_sum" in c:
+                e["l2_hit_rate"] = round(c["TCC_HIT_sum"] / max(1.0, c["TCC_HIT_sum"] + c["TCC_MISS_sum"]), 4)
+            bpp = _algorithmic_bytes_per_point(k)
+            if bpp is not None:
+                e["algorithmic_bytes_per_launch"] = bpp * npts
+                e["traffic_over_algorithmic"] = round((rd + wr) / (bpp * npts), 4)
+            kernels.append(e)
+        doc = {"workload": name, "kernel_source_hash": kernel_source_hash(),
+               "commands": [f"rocprofv3 --pmc {' '.join(cs)} --output-format csv -d gpurun_out/pmc/{p}_{w} "
+                            f"-o run -- python3 bench.py --profile {w} --steps 10"
+                            for w in (what, "copy") for p, cs in PMC_PASSES.items()
+                            if w == what or p in ("fetch", "write")]
+                           + ["python3 bench.py --pmc-summary gpurun_out/pmc"],
+               "calibration": calibration, "kernels": kernels}
+        path = os.path.join(out_dir, f"pmc_traffic_{name}.json")
+        with open(path, "w") as fh:
+            json.dump(doc, fh, indent=1)
+            fh.write("\n")
+        written.append(path)
+    return written
 
 
 def time_steps(lat, steps, torch, stream_only=False):
@@ -419,6 +549,10 @@ def main():
                          "cavity (256^3 FP32/FP16/BF16 steps and the FP32 stream-only step), spheres "
                          "(sphere duct, every storage, AB and AA), adjoint (256^3 reverse sweep, T=8, "
                          "K=4), copy (the copy probe with and without load hints, 2 GiB)")
+    ap.add_argument("--pmc-summary", metavar="DIR", default=None,
+                    help="summarise the rocprofv3 counter passes under DIR (<pass>_<workload> "
+                         "folders from --profile runs) into profiles/pmc_traffic_*.json and exit; "
+                         "runs on the host, no GPU")
     ap.add_argument("--copy-only", action="store_true",
                     help="run only the copy probe (2 GiB float32, 20 launches): counter calibration")
     args = ap.parse_args()
@@ -427,6 +561,11 @@ def main():
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path is "
               "single-GPU; multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
+
+    if args.pmc_summary:
+        for path in pmc_summary(args.pmc_summary, os.path.join(ROOT, "profiles")):
+            print(path)
+        return
 
     import torch
     import paper_1309_1983_amd
@@ -498,7 +637,7 @@ def main():
     lat.close()
     mlups = N / ms / 1e3
     achieved = BYTES_PER_POINT["f32"] * N / (ms * 1e-3) / 1e9
-    traffic = load_traffic(workload)
+    traffic = load_traffic(workload, kernel_name)
     line = {
         "metric": "MLUPS and % HBM roofline, D3Q19 FP32 256^3; FP16-storage and adjoint MLUPS",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
