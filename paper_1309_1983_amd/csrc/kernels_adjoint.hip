@@ -248,9 +248,12 @@ struct FlagBytes<4> {
 // 16-byte shifted accesses of the forward vector kernel (gather_vec); each
 // point then runs the same adj_cell arithmetic as the one-point kernel, so
 // b and dL/dF agree with it bit for bit. The launch bound asks for three
-// waves per SIMD: for two points per work-item that is 168 VGPRs with 24
-// bytes of spill per work-item instead of 174 VGPRs at two waves, and the
-// reverse sweep measured 11% faster (256^3 duct on MI355X).
+// waves per SIMD (168 VGPRs for two points per work-item): against two waves
+// at 174 VGPRs the reverse sweep measured 11% faster (256^3 duct on MI355X).
+// To fit that bound without spilling, a per-point force is read point by
+// point inside the cell loop and dL/dF is read after it, so neither is held
+// across the loop: with a force field this removed 20 bytes of scratch per
+// work-item (reverse-step counter traffic was 1.11x its 264 bytes per point).
 template <int FM, bool DIRECT, int VW>
 __global__ __launch_bounds__(256, 3) void k_adj_stepv(const float* __restrict__ s,
                                                    const float* __restrict__ bin,
@@ -298,25 +301,15 @@ __global__ __launch_bounds__(256, 3) void k_adj_stepv(const float* __restrict__ 
 #pragma unroll
         for (int j = 0; j < VW; ++j) mm[j] = 0u;
         if (flw & (ONES * NEAR_MOVING)) load_words<VW>(mmask, c0, mm);
-        float F[3][VW];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (FM == FORCE_FIELD) {
-                const Vt f = ldv<VW>(ff + k * N, c0);
-#pragma unroll
-                for (int j = 0; j < VW; ++j) F[k][j] = f[j];
-            } else {
-                const float fu = FM == FORCE_UNIFORM ? (k == 0 ? a.Fx : (k == 1 ? a.Fy : a.Fz)) : 0.0f;
-#pragma unroll
-                for (int j = 0; j < VW; ++j) F[k][j] = fu;
-            }
-        }
-        Vt gv[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) gv[k] = ldv<VW>(gF + k * N, c0);
+        float ga[3][VW];
 #pragma unroll
         for (int j = 0; j < VW; ++j) {
             const bool sol = (solid >> (8 * j)) & 1u;
+            float F[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                F[k] = FM == FORCE_FIELD ? ld(ff + k * N, c0 + (uint32_t)j)
+                                         : (FM == FORCE_UNIFORM ? (k == 0 ? a.Fx : (k == 1 ? a.Fy : a.Fz)) : 0.0f);
             float av[Q], h[Q], b[Q], gx, gy, gz, tt;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
@@ -324,14 +317,21 @@ __global__ __launch_bounds__(256, 3) void k_adj_stepv(const float* __restrict__ 
                 h[i] = hq[i][j] - weight(i);
                 if (i > 0 && ((mm[j] >> i) & 1u)) h[i] = h[i] + a.mw[i];
             }
-            adj_cell<FORCE>(av, h, F[0][j], F[1][j], F[2][j], a, inv_tau2, b, gx, gy, gz, tt);
+            adj_cell<FORCE>(av, h, F[0], F[1], F[2], a, inv_tau2, b, gx, gy, gz, tt);
 #pragma unroll
             for (int i = 0; i < Q; ++i) aq[i][j] = sol ? 0.0f : b[i];
-            if (!sol) {
-                gv[0][j] = gv[0][j] + gx;
-                gv[1][j] = gv[1][j] + gy;
-                gv[2][j] = gv[2][j] + gz;
-                tsum += (double)tt;
+            ga[0][j] = gx; ga[1][j] = gy; ga[2][j] = gz;
+            if (!sol) tsum += (double)tt;
+        }
+        Vt gv[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) gv[k] = ldv<VW>(gF + k * N, c0);
+#pragma unroll
+        for (int j = 0; j < VW; ++j) {
+            if (!((solid >> (8 * j)) & 1u)) {
+                gv[0][j] = gv[0][j] + ga[0][j];
+                gv[1][j] = gv[1][j] + ga[1][j];
+                gv[2][j] = gv[2][j] + ga[2][j];
             }
         }
 #pragma unroll
