@@ -54,3 +54,48 @@ def test_cavity_profiles_converge_with_resolution():
     rms, rms_orders = cavity.resolution_differences(res, "rms")
     print(f"Re 20: max profile differences {diffs} (order {orders}); RMS {rms} (order {rms_orders})")
     assert diffs[1] < diffs[0] / 1.8 and rms[1] < rms[0] / 1.8
+
+
+def _oracle_profiles(r, L):
+    from paper_1309_1983_amd import cavity
+    nx, n, _ = cavity.box_shape(L)
+    olat = oracle_lattice((nx, n, n), np.float32(r.tau), flags=cavity.cavity_flags(L),
+                          uw=(np.float32(r.u_lid), 0, 0))
+    s = olat.run(oracle.init_equilibrium(nx * n * n), r.steps)
+    _, uo = olat.macros(s)
+    uo = uo.reshape(3, n, n, nx)
+    m = 1 + L // 2
+    return uo[0, m, 1:L + 2, m] / np.float32(r.u_lid), uo[1, m, m, 1:L + 2] / np.float32(r.u_lid)
+
+
+@pytest.mark.timeout(300)
+def test_re100_cavity_matches_oracle():
+    """Re 100, the paper's lowest validation Reynolds number (Section 5), at
+    L = 32 with tau 0.6 (Eq. (8): lid speed 0.104), run from rest to a steady
+    state on the GPU; the oracle runs the same number of steps in FP64."""
+    from paper_1309_1983_amd import cavity
+    L = 32
+    r = cavity.run(100, L, tau=0.6, tol=1e-5)
+    assert r.converged and r.finite
+    ux, uy = _oracle_profiles(r, L)
+    err = max(np.max(np.abs(r.ux - ux)), np.max(np.abs(r.uy - uy)))
+    print(f"Re 100 L {L}: {r.steps} steps, centreline |u_gpu - u_oracle| / u_lid = {err:.2e}; "
+          f"min u_x/U {r.ux.min():.4f} at y/L {r.y[np.argmin(r.ux)]:.3f}")
+    assert err <= 1e-4
+    # the primary vortex: the vertical centreline's u_x reverses below the lid
+    assert r.ux.min() < -0.1 and 0.3 < r.y[np.argmin(r.ux)] < 0.7
+
+
+@pytest.mark.timeout(300)
+def test_re100_profiles_converge_with_resolution():
+    """Re 100 at L = 32, 64, 128 with tau 0.6 fixed (diffusive scaling). The
+    lid's singular corners cap the observed order near one: each doubling
+    must shrink the profile differences by at least 1.6."""
+    from paper_1309_1983_amd import cavity
+    res = [cavity.run(100, L, tau=0.6, tol=1e-5) for L in (32, 64, 128)]
+    assert all(r.converged and r.finite for r in res)
+    diffs, orders = cavity.resolution_differences(res)
+    rms, rms_orders = cavity.resolution_differences(res, "rms")
+    print(f"Re 100: steps {[r.steps for r in res]}; max profile differences {diffs} (order {orders}); "
+          f"RMS {rms} (order {rms_orders})")
+    assert diffs[1] < diffs[0] / 1.6 and rms[1] < rms[0] / 1.6
