@@ -75,6 +75,9 @@ struct lbm_lattice {
     bool vec_ok = true;            // vector kernels allowed (cells_per_lane != 1)
     int bx4 = 64, by4 = 1;         // work-group of the vector kernel
     bool flat = false;             // vector AB step on a one-dimensional grid per plane
+    bool alt4 = false;             // bfloat16, eight points: four points while a force is set
+    int alt_bx4 = 64, alt_by4 = 1; // work-group of that four-point launch
+    bool alt_flat = false;
     bool onsite = false;           // has on-site velocity nodes (flags 3, 4)
     bool early = false;            // FP32 vector AB step gathers before the flag branches
     unsigned shmem4 = 0;           // LDS reserved per vector-step work-group (residency cap)
@@ -152,6 +155,23 @@ int force_mode(const lbm_lattice* L)
     return lbmk::FORCE_NONE;
 }
 
+// Points per work-item and launch shape of the vector AB step for the
+// lattice's current force mode. A bfloat16 lattice laid out with eight points
+// per work-item runs four while a body force is set: the eight-point kernel
+// with a force needs 185 VGPRs (two waves per SIMD; bounded to three it
+// spills), and four points measured 2-6% faster with a uniform force or a
+// force field on MI355X (256^3 cavity, 128x128x256 sphere duct); without a
+// force eight points are 4-5% faster.
+struct VecShape {
+    int cpl, bx4, by4;
+    bool flat;
+};
+VecShape vec_shape(const lbm_lattice* L)
+{
+    if (L->alt4 && force_mode(L) != lbmk::FORCE_NONE) return {4, L->alt_bx4, L->alt_by4, L->alt_flat};
+    return {L->cpl, L->bx4, L->by4, L->flat};
+}
+
 lbmk::StepArgs step_args(const lbm_lattice* L)
 {
     lbmk::StepArgs a{};
@@ -168,7 +188,8 @@ lbmk::StepArgs step_args(const lbm_lattice* L)
         a.mw[i] = (float)(6.0 * (double)d3q19::weight(i) * eu);
     }
     for (int k = 0; k < 3; ++k) a.uw[k] = L->uw[k];
-    a.gx = L->flat ? (uint32_t)(L->nx / L->cpl) : 0u;
+    const VecShape v = vec_shape(L);
+    a.gx = v.flat ? (uint32_t)(L->nx / v.cpl) : 0u;
     a.early = L->early ? 1u : 0u;
     return a;
 }
@@ -178,8 +199,9 @@ lbmk::Launch launch_of(const lbm_lattice* L) { return lbmk::make_launch(L->dims,
 // Only valid when the lattice uses the vector kernel (cpl > 1).
 lbmk::Launch launch4_of(const lbm_lattice* L)
 {
-    if (L->flat) {
-        const unsigned long long groups = (unsigned long long)(L->nx / L->cpl) * (unsigned long long)L->ny;
+    const VecShape v = vec_shape(L);
+    if (v.flat) {
+        const unsigned long long groups = (unsigned long long)(L->nx / v.cpl) * (unsigned long long)L->ny;
         lbmk::Launch la;
         la.block = dim3(64, 1, 1);
         la.grid = dim3((unsigned)((groups + 63) / 64), 1, (unsigned)L->nz);
@@ -188,8 +210,8 @@ lbmk::Launch launch4_of(const lbm_lattice* L)
         return la;
     }
     d3q19::Dims q = L->dims;
-    q.nx = L->nx / L->cpl;   // the grid counts groups of cpl points along x
-    lbmk::Launch la = lbmk::make_launch(q, L->bx4, L->by4, L->stream);
+    q.nx = L->nx / v.cpl;   // the grid counts groups of cpl points along x
+    lbmk::Launch la = lbmk::make_launch(q, v.bx4, v.by4, L->stream);
     la.shmem = L->shmem4;
     return la;
 }
@@ -578,6 +600,16 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
         }
         g_last_error.clear();
     }
+    if (L->storage == LBM_STORAGE_BF16 && L->cpl == 8 && opt.cells_per_lane == 0) {
+        // the four-point launch taken while a body force is set
+        lbm_options o4 = opt;
+        o4.cells_per_lane = 4;
+        Layout l4;
+        if (resolve_layout(nx, ny, nz, o4, l4) == LBM_OK && l4.cpl == 4) {
+            L->alt4 = true; L->alt_bx4 = l4.bx4; L->alt_by4 = l4.by4; L->alt_flat = l4.flat;
+        }
+        g_last_error.clear();
+    }
     const bool early_ok = L->storage == LBM_STORAGE_F32 && L->pattern == LBM_PATTERN_AB && L->cpl > 1 && !L->onsite;
     L->early = early_ok && (opt.gather_mode == 2 ||
                             (opt.gather_mode == 0 && porous));
@@ -705,7 +737,7 @@ lbm_status lbm_step_kernel_name(lbm_lattice* L, char* buf, size_t cap)
     DeviceGuard guard(L->device);
     const bool vector = L->pattern == LBM_PATTERN_AB && L->cpl > 1;
     const void* fn = nullptr;
-    HIPCHK(L, lbmk::resolve_step_kernel(vector, L->storage, L->pattern, L->parity, L->cpl, true, force_mode(L),
+    HIPCHK(L, lbmk::resolve_step_kernel(vector, L->storage, L->pattern, L->parity, vec_shape(L).cpl, true, force_mode(L),
                                         L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags, L->d_smask, L->d_mmask,
                                         L->d_force, step_args(L), vector ? launch4_of(L) : launch_of(L), L->onsite,
                                         &fn));
@@ -1162,7 +1194,7 @@ lbm_status run_steps(lbm_lattice* L, int n, bool collide, float* rho, float* u)
         float* mr = s == n - 1 ? rho : nullptr;
         float* mu = s == n - 1 ? u : nullptr;
         if (L->pattern == LBM_PATTERN_AB && L->cpl > 1) {
-            HIPCHK(L, lbmk::launch_step_abv(L->storage, L->cpl, collide, fm, L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags,
+            HIPCHK(L, lbmk::launch_step_abv(L->storage, vec_shape(L).cpl, collide, fm, L->d_f[L->cur], L->d_f[L->cur ^ 1], L->d_flags,
                                             L->d_smask, L->d_mmask, L->d_force, args, LA4, mr, mu, L->onsite));
             L->cur ^= 1;
         } else if (L->pattern == LBM_PATTERN_AB) {

@@ -178,3 +178,38 @@ def test_stream_switches_keep_order():
     lat.close()
     fl = torch.from_numpy(flags == 0)
     assert torch.equal(got[:, fl], ref[:, fl])
+
+
+def test_bfloat16_takes_four_points_while_a_force_is_set():
+    """A bfloat16 lattice laid out with eight points per work-item steps with
+    four while a body force (uniform or a field) is set, and with eight again
+    once it is cleared: the named kernel follows, and the state equals the
+    one-point kernel's bit for bit through the switches."""
+    from paper_1309_1983_amd import Lattice
+    shape = (256, 9, 7)
+    N = int(np.prod(shape))
+    flags = W.random_flags(N, seed=70, solid_fraction=0.1, moving_fraction=0.05)
+    s0 = near_rest_state(N, 71)
+    ff = torch.from_numpy(W.random_force_field(N, 72, 1e-5).astype(np.float32))
+
+    def run(**kw):
+        lat = Lattice(*shape, 0.7, flags=flags, storage="bf16", **kw)
+        lat.set_wall_velocity(0.05, -0.02, 0.03)
+        lat.set_populations(torch.from_numpy(s0))
+        names = []
+        for force in (None, (1e-5, 2e-5, -1e-5), ff, (0.0, 0.0, 0.0)):
+            if force is not None:
+                lat.set_force(force)
+            names.append(lat.step_kernel_name())
+            lat.step(3)
+        out = lat.populations().cpu().numpy()
+        lat.close()
+        return out, names
+
+    got, names = run()
+    assert ["true, 8," in n for n in names] == [True, False, False, True], names
+    assert ["true, 4," in n for n in names] == [False, True, True, False], names
+    ref, ref_names = run(cells_per_lane=1)
+    assert all("k_step_ab<" in n for n in ref_names), ref_names
+    fl = flags == 0
+    np.testing.assert_array_equal(got[:, fl], ref[:, fl])
