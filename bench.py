@@ -653,6 +653,9 @@ def main():
                      "bytes_per_point": BYTES_PER_POINT["f32"],
                      "kernel": kernel_name},
     }
+    # the paper's own figure, on other hardware: context only, not vs_baseline
+    line["paper_context"] = {"mlups": 1036.41, "device": "Tesla K20c (measured 157.89 GB/s)",
+                             "config": "FP32 D3Q19, 192^3, block 64 (Table 2)"}
     log(f"FP32 AB: {ms:.4f} ms/step, {mlups:.0f} MLUPS, {achieved:.0f} GB/s "
         f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s)")
     if sweep is not None:
