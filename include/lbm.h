@@ -100,8 +100,10 @@ typedef struct lbm_options {
                              for 16-bit storage when nx % 8 == 0 and either
                              nx >= 256 or at least 8% of the fluid points have
                              a solid neighbour, else 4 when nx % 4 == 0,
-                             else 1; bfloat16 steps taken while a body force
-                             is set use 4 where the automatic choice is 8);
+                             else 1; 1 for lattices of at most 2^18 points
+                             without solid points; bfloat16 steps taken while
+                             a body force is set use 4 where the automatic
+                             choice is 8);
                              1; 4; or 8 (16-bit storage only: 16-byte
                              accesses). 4 and 8 need
                              nx to be a multiple of them and

@@ -60,7 +60,7 @@ def test_gather_modes_are_bitwise_equal_f32(case):
     ref = _run(shape, 0.8, flags, s0, 5, ff=ff, cells_per_lane=1)
     fl = flags == 0
     for gm in ("flags_first", "early", "auto"):
-        got = _run(shape, 0.8, flags, s0, 5, ff=ff, gather_mode=gm)
+        got = _run(shape, 0.8, flags, s0, 5, ff=ff, gather_mode=gm, cells_per_lane=4)
         np.testing.assert_array_equal(got[0][:, fl], ref[0][:, fl], err_msg=gm)
         np.testing.assert_array_equal(got[1], ref[1])
         np.testing.assert_array_equal(got[2], ref[2])
@@ -213,3 +213,26 @@ def test_bfloat16_takes_four_points_while_a_force_is_set():
     assert all("k_step_ab<" in n for n in ref_names), ref_names
     fl = flags == 0
     np.testing.assert_array_equal(got[:, fl], ref[:, fl])
+
+
+def test_small_solid_free_lattices_take_one_point_per_work_item():
+    """With the automatic width, a lattice of at most 2^18 points without
+    solid points steps one point per work-item; a solid point, or more points,
+    keeps the vector step. Results do not depend on the choice."""
+    from paper_1309_1983_amd import Lattice
+    cases = [((32, 32, 32), False, "k_step_ab<"), ((32, 32, 32), True, "k_step_abv<"),
+             ((72, 64, 64), False, "k_step_abv<")]
+    for shape, one_solid, kernel in cases:
+        N = int(np.prod(shape))
+        flags = np.zeros(N, dtype=np.uint8)
+        if one_solid:
+            flags[N // 2] = 1
+        s0 = near_rest_state(N, 95)
+        lat = Lattice(*shape, 0.8, flags=flags)
+        assert kernel in lat.step_kernel_name(), (shape, one_solid, lat.step_kernel_name())
+        lat.close()
+        auto = _run(shape, 0.8, flags, s0, 4, force=(1e-5, 0, -1e-5))
+        for cpl in (1, 4):
+            got = _run(shape, 0.8, flags, s0, 4, force=(1e-5, 0, -1e-5), cells_per_lane=cpl)
+            fl = flags == 0
+            np.testing.assert_array_equal(got[0][:, fl], auto[0][:, fl])
