@@ -260,7 +260,7 @@ __device__ __forceinline__ void load_words(const uint32_t* __restrict__ base, ui
 // On the 256^3 cavity (2% near-wall points) the unconditional mask loads cost
 // more than the overlap gains, so the caller enables it by geometry.
 // ---------------------------------------------------------------------------
-template <int SIGN, int VW, bool EARLY = false, class B>
+template <int SIGN, int VW, bool EARLY = false, bool DROP_PRIO = false, class B>
 __device__ __forceinline__ void gather_vec(const B* __restrict__ src, const Dims& d, uint32_t z,
                                            uint32_t zm, uint32_t zp, uint32_t orow, uint32_t oym,
                                            uint32_t oyp, uint32_t x0, bool end0, bool endL,
@@ -306,6 +306,8 @@ __device__ __forceinline__ void gather_vec(const B* __restrict__ src, const Dims
         else
             q[i] = ldv<VW>(P, r + xs);
     }
+    // the caller raised the wave's priority for issuing these loads
+    if constexpr (DROP_PRIO) __builtin_amdgcn_s_setprio(0);
     if constexpr (EARLY) {
 #pragma unroll
         for (int j = 0; j < VW; ++j) smw[j] = near_wall ? early_mask[j] : 0u;
