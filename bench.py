@@ -147,6 +147,7 @@ def pmc_summary(root, out_dir):
     def mean(v):
         return sum(v) / len(v)
 
+    rel = os.path.relpath(root, ROOT) if os.path.abspath(root).startswith(ROOT + os.sep) else root
     cal = {p: _pmc_table(os.path.join(root, f"{p}_copy")) for p in ("fetch", "write")}
     copies = sorted(cal["fetch"])
     fetch_kib = mean([mean(cal["fetch"][k]["FETCH_SIZE"]) for k in copies])
@@ -186,11 +187,11 @@ def pmc_summary(root, out_dir):
                 e["traffic_over_algorithmic"] = round((rd + wr) / (bpp * npts), 4)
             kernels.append(e)
         doc = {"workload": name, "kernel_source_hash": kernel_source_hash(),
-               "commands": [f"rocprofv3 --pmc {' '.join(cs)} --output-format csv -d gpurun_out/pmc/{p}_{w} "
+               "commands": [f"rocprofv3 --pmc {' '.join(cs)} --output-format csv -d {rel}/{p}_{w} "
                             f"-o run -- python3 bench.py --profile {w} --steps 10"
                             for w in (what, "copy") for p, cs in PMC_PASSES.items()
                             if w == what or p in ("fetch", "write")]
-                           + ["python3 bench.py --pmc-summary gpurun_out/pmc"],
+                           + [f"python3 bench.py --pmc-summary {rel}"],
                "calibration": calibration, "kernels": kernels}
         path = os.path.join(out_dir, f"pmc_traffic_{name}.json")
         with open(path, "w") as fh:
