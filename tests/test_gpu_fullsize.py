@@ -2,7 +2,8 @@
 benchmark times (default work-group shape).
 
 - 256^3 lid-driven cavity: full-domain parity after 100 steps from a random
-  near-rest state (every point, every direction, <= 1e-5);
+  near-rest state (every point, every direction, <= 1e-5), and the FP16/BF16
+  offset errors against the same oracle run bounded;
 - 256^3 and 512^3 lid-driven cavities: 3 steps from a random near-rest
   state, sampled points checked against the oracle evolved in each point's
   7^3 neighbourhood (exact: 3 pull steps only reach 3 points away);
@@ -45,32 +46,41 @@ def _sample_cells(n, flags, k, seed):
 
 @pytest.mark.timeout(600)
 def test_cavity256_full_domain_100_steps():
-    """The benchmarked workload (256^3 cavity, tau 0.6, lid 0.1 along +x, FP32,
-    two arrays, default launch) against the FP64 oracle on every point after
-    100 steps. The start is a random near-rest equilibrium rather than rest,
-    so that every point carries a non-trivial state from the first step."""
+    """The benchmarked workload (256^3 cavity, tau 0.6, lid 0.1 along +x, two
+    arrays, default launch) against the FP64 oracle on every point after 100
+    steps: FP32 within 1e-5, and the FP16/BF16-offset runs within the
+    accuracy stated for them (measured on MI355X: 3.0e-4 and 2.5e-3 relative
+    in f; bounds about three times that). The start is a random near-rest
+    equilibrium rather than rest, so that every point carries a non-trivial
+    state from the first step."""
     from paper_1309_1983_amd import Lattice
     n, tau, lid, steps = 256, 0.6, 0.1, 100
     flags = W.cavity_flags(n, n, n)
     N = n ** 3
     s0 = near_rest_state(N, 31, 0.01, 0.02)
-    lat = Lattice(n, n, n, tau, flags=flags)
-    lat.set_wall_velocity(lid)
-    lat.set_populations(torch.from_numpy(s0))
-    lat.step(steps)
-    got = lat.populations().cpu().numpy()
-    lat.close()
+    got = {}
+    for storage in ("f32", "f16", "bf16"):
+        lat = Lattice(n, n, n, tau, flags=flags, storage=storage)
+        lat.set_wall_velocity(lid)
+        lat.set_populations(torch.from_numpy(s0))
+        lat.step(steps)
+        got[storage] = lat.populations().cpu().numpy()
+        lat.close()
     torch.cuda.empty_cache()
     olat = oracle_lattice((n, n, n), tau, flags=flags, uw=(lid, 0, 0))
     ref = olat.run(s0.astype(np.float64), steps)
     del s0
     fl = flags == 0
-    err = 0.0
+    err = {k: 0.0 for k in got}
     for i in range(19):    # one direction at a time keeps the host copies small
         r = ref[i, fl]
-        err = max(err, float(np.max(np.abs(got[i, fl].astype(np.float64) - r) / np.abs(r))))
-    print(f"256^3 cavity, all {int(fl.sum())} fluid points after {steps} steps: max rel |df| = {err:.3e}")
-    assert err <= 1e-5
+        for k, f in got.items():
+            err[k] = max(err[k], float(np.max(np.abs(f[i, fl].astype(np.float64) - r) / np.abs(r))))
+    print(f"256^3 cavity, all {int(fl.sum())} fluid points after {steps} steps: max rel |df| = "
+          f"{err['f32']:.3e} (FP32), {err['f16']:.3e} (FP16 offsets), {err['bf16']:.3e} (BF16 offsets)")
+    assert err["f32"] <= 1e-5
+    assert err["f16"] <= 1e-3
+    assert err["bf16"] <= 1e-2
 
 
 @pytest.mark.parametrize("n,tau,lid", [(256, 0.6, 0.1), (512, 0.55, 0.05)])
