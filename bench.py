@@ -49,11 +49,22 @@ def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
+def _code_of(text):
+    """Source text without // comments, trailing blanks and blank lines: what
+    the compiler sees of the step kernels (the hashed files use no block
+    comments and no // inside string literals)."""
+    lines = (line.split("//", 1)[0].rstrip() for line in text.splitlines())
+    return "\n".join(line for line in lines if line)
+
+
 def kernel_source_hash():
+    """Hash of the step kernels' code (comments and layout left out), stored
+    with the counter summaries so that the benchmark reports traffic only for
+    the kernels the counters were taken on."""
     h = hashlib.sha256()
     for name in ("d3q19.hpp", "kernels_step.hip", "kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_1309_1983_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1309_1983_amd", "csrc", name), encoding="utf-8") as fh:
+            h.update(_code_of(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

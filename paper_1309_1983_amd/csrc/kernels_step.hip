@@ -192,9 +192,6 @@ void k_step_abv(const typename St::bits_t* __restrict__ src,
     using FW = typename FlagWord<VW>::t;
     constexpr FW ONES = FlagWord<VW>::ones;
     const Dims& d = a.d;
-    // FLAT: rows whose group count is not a multiple of the wave width run
-    // on a one-dimensional grid over the plane (a.gx groups per row), so
-    // that every wave is full.
     // FP32 flags-first form: the wave issues its flag and gather loads at
     // raised priority and drops it once the 19 loads are out, so that waves
     // starting while others collide get their loads into the memory pipeline
@@ -203,6 +200,9 @@ void k_step_abv(const typename St::bits_t* __restrict__ src,
     // slower, so they run at the default priority.
     constexpr bool PRIO = sizeof(B) == 4 && !EARLY;
     if constexpr (PRIO) __builtin_amdgcn_s_setprio(2);
+    // FLAT: rows whose group count is not a multiple of the wave width run
+    // on a one-dimensional grid over the plane (a.gx groups per row), so
+    // that every wave is full.
     const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
     int x0, y;
     if (FLAT) {
