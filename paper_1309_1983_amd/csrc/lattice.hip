@@ -599,6 +599,7 @@ lbm_status lbm_create_ex(int nx, int ny, int nz, float tau, const uint8_t* flags
         // and the grid holds too few waves to fill the GPU: on MI355X the
         // 32^3 periodic step ran 3.5 us against 6.5 us, 64^3 12% faster
         L->cpl = 1;
+        L->flat = false;
     }
     if (porous && L->storage != LBM_STORAGE_F32 && L->cpl == 4 && opt.cells_per_lane == 0 && nx % 8 == 0) {
         // 16-bit storage on porous geometry: eight points per work-item
