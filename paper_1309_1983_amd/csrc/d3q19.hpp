@@ -280,11 +280,15 @@ __device__ __forceinline__ void gather_vec(const B* __restrict__ src, const Dims
     uint32_t smw[VW];   // neighbour mask, loaded first unless all planes are loaded
 #pragma unroll
     for (int j = 0; j < VW; ++j) smw[j] = 0u;
+    // 16-bit storage, four points per work-item: the all-planes form loads
+    // only the planes some work-item of the wave bounces from, by the wave's
+    // OR of the neighbour masks, which are then loaded before the gather
+    constexpr bool WAVE_OR = sizeof(B) == 2 && VW == 4;
     if constexpr (!EARLY) {
         // wave-wide count of work-items with near-wall points
         const int nw_lanes = __builtin_popcountll(__builtin_amdgcn_ballot_w64(near_wall));
         all_planes = sizeof(B) == 2 && nw_lanes > 4;
-        if (near_wall && !all_planes) load_words<VW>(smask, c0, smw);
+        if (near_wall && (!all_planes || WAVE_OR)) load_words<VW>(smask, c0, smw);
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -350,10 +354,26 @@ __device__ __forceinline__ void gather_vec(const B* __restrict__ src, const Dims
     if (near_wall && all_planes) {
         const B* base = plane(src, d, 0, z);
         Vt loc[Q];
-#pragma unroll
-        for (int i = 1; i < Q; ++i) loc[i] = ldv<VW>(base, (uint32_t)i * d.nxy + o0);
         uint32_t sm[VW];
-        load_words<VW>(smask, c0, sm);
+        if constexpr (WAVE_OR) {
+            uint32_t lane_or = 0;
+#pragma unroll
+            for (int j = 0; j < VW; ++j) {
+                sm[j] = smw[j];
+                lane_or |= smw[j];
+            }
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int bit = SIGN > 0 ? i : OPP[i];
+                loc[OPP[i]] = q[i];   // not read unless some work-item needs the plane
+                if (__builtin_amdgcn_ballot_w64((lane_or >> bit) & 1u) != 0ull)
+                    loc[OPP[i]] = ldv<VW>(base, (uint32_t)OPP[i] * d.nxy + o0);
+            }
+        } else {
+#pragma unroll
+            for (int i = 1; i < Q; ++i) loc[i] = ldv<VW>(base, (uint32_t)i * d.nxy + o0);
+            load_words<VW>(smask, c0, sm);
+        }
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
             const int bit = SIGN > 0 ? i : OPP[i];
