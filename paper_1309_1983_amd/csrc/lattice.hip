@@ -441,7 +441,8 @@ d3q19::Dims dims_of(int nx, int ny, int nz)
 // duct, 10%: 126.7 -> 114.1 us per step; 256^3 cavity, 2%: 3% slower) and
 // the 16-bit AB step takes eight points per work-item when rows allow it
 // (sphere duct 128 x 128 x 256: FP16 77.0 -> 69.1 us, BF16 79.4 -> 73.8 us;
-// the plain 128-wide duct, 3%, is 1-6% faster with four).
+// the plain 128-wide duct, 3%, is 1-6% faster with four). Bfloat16 steps
+// taken while a body force is set still launch four (vec_shape).
 constexpr double POROUS_MIN_NEAR_FRACTION = 0.08;
 // Lattices without solid points up to this size step with one point per
 // work-item when the width is automatic.
